@@ -1,0 +1,20 @@
+"""The oracle still produces the frozen values in tests/golden/hth_golden.json
+(written by tests/golden/make_golden.py from the oracle alone)."""
+import json
+import os
+
+from paper_2104_08865_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hth_golden.json")
+
+
+def test_oracle_matches_golden(oracle_lib):
+    doc = json.load(open(GOLDEN))
+    ents = {}
+    for row in doc["cases"]:
+        s = row["user_seed"]
+        if s not in ents:
+            ents[s] = oracle_lib.expand_seed(s)
+        data = wl.random_bytes(row["bytes_seed"], row["length"])
+        h = oracle_lib.hash_bytes(ents[s], data.tobytes(), row["width"])
+        assert bytes(h).hex() == row["hash"], row
