@@ -1,0 +1,134 @@
+/*
+ * libhth: HalftimeHash on AMD Instinct MI355X (gfx950).
+ *
+ * The hash family H(s, x) of the paper (§1: a map from a seed s and a byte
+ * string x to a 16, 24, 32 or 40 byte value, almost universal among strings
+ * of equal length, §2) computed by hand-written HIP kernels.  Every result is
+ * bit-for-bit the value the family defines; there is no approximate mode.
+ *
+ * Family (paper §5.1, §6.1): b = 8 64-bit words per block, code symbols of
+ * w = 3 words, tree fanout f = 8; per width (d, e, k) = (6,7,2), (7,9,3),
+ * (7,10,4), (5,9,5); the k x e combine matrices printed in §5.1; systematic
+ * GF(8) MDS erasure codes of distance k; k trees of NH-variant nodes (§3.2)
+ * over the EHC outputs with the stack construction of Eq. (3) in base 8;
+ * one final NH per tree (§5.2); the tail hashed k times with Toeplitz keys
+ * (§6.1); an NH of the byte length added to every output word (§2 asks for
+ * the length to be appended so that different lengths also separate).
+ *
+ * Conventions of every call:
+ *   - Return value: HTH_OK (0) or a negative hth_status.  On error nothing
+ *     is enqueued and no output is written; hth_last_error() gives a
+ *     message (thread-local, valid until the next call on the thread).
+ *   - "device pointer": memory of the current HIP device (hipMalloc, torch
+ *     CUDA tensors).  "host pointer": ordinary process memory.
+ *   - Calls that take a stream enqueue work on it and return without
+ *     waiting; inputs must stay valid and unmodified, and outputs must not
+ *     be read, until that work is complete.  Stream 0 is the null stream.
+ *   - All calls are thread-safe.  Two hth_hash_batch calls in flight on
+ *     different streams use different scratch areas and may overlap.
+ */
+#ifndef HTH_H
+#define HTH_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hth_status;
+#define HTH_OK 0
+#define HTH_E_INVALID (-1)   /* bad argument (null pointer, unsupported width, ...) */
+#define HTH_E_OOM (-2)       /* device or host allocation failed */
+#define HTH_E_HIP (-3)       /* a HIP runtime call failed */
+#define HTH_E_BUSY (-4)      /* not ready yet / admission deferred */
+#define HTH_E_TOO_LARGE (-5) /* request exceeds a configured limit */
+
+/* Thread-local description of the last failure on this thread. */
+const char *hth_last_error(void);
+
+/* Number of 64-bit entropy words of a seed (all four widths together). */
+size_t hth_entropy_words(void);
+
+/* ------------------------------------------------------------------------ */
+/* Seeds.  The family is parameterised by random entropy words (the paper's */
+/* "input entropy", §2, §6.2).  A seed object holds them in device memory,  */
+/* is immutable after creation and may be shared by any number of streams.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hth_seed hth_seed;
+
+/* Fill the entropy of all widths from a 64-bit user seed: word i is output i
+   of splitmix64 started at state user_seed (Steele, Lea and Flood 2014).
+   The host computes the words and copies them to the device on `stream`.
+   *out is owned by the caller until hth_seed_free.
+   Errors: HTH_E_INVALID (out null), HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_expand_seed(uint64_t user_seed, hth_seed **out, hipStream_t stream);
+
+/* Same, from caller-provided raw entropy: `words` is a host pointer to
+   n_words = hth_entropy_words() words (layout: for each width 16, 24, 32, 40
+   in turn, [EHC keys e*w][tree keys k*20*7][final keys k*20*7*8]
+   [tail keys 8*d*w + k - 1][length keys k]).  The words are copied; the
+   caller keeps ownership of `words`.
+   Errors: HTH_E_INVALID (null pointer or wrong n_words), HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_seed_from_entropy(const uint64_t *words, size_t n_words, hth_seed **out,
+                                 hipStream_t stream);
+
+/* Copy a seed's entropy words to host memory (n_words must equal
+   hth_entropy_words()).  Synchronous. */
+hth_status hth_seed_entropy(const hth_seed *seed, uint64_t *host_words, size_t n_words);
+
+/* Release a seed.  Work already enqueued with it must have completed.
+   Null is accepted. */
+hth_status hth_seed_free(hth_seed *seed);
+
+/* ------------------------------------------------------------------------ */
+/* Batched hashing.                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Hash `count` byte strings with one family member H(seed, .).
+ *
+ *   bytes    device pointer; string i is bytes[offsets[i], offsets[i] +
+ *            lengths[i]).  No alignment is required; strings may overlap.
+ *   offsets  device pointer to count uint64_t.
+ *   lengths  device pointer to count uint64_t.
+ *   out      device pointer to count * out_width bytes; row i receives the
+ *            out_width-byte value of string i: k = out_width / 8 words,
+ *            little endian, tree 0 first.
+ *   out_width  16, 24, 32 or 40.
+ *
+ * out[i] depends only on the seed and string i, never on the rest of the
+ * batch.  The call enqueues a short planning step and one persistent kernel
+ * on `stream` and returns.  Scratch memory comes from a per-stream workspace
+ * that the library grows on the host as `count` grows (hth_reserve
+ * pre-allocates it, e.g. before stream capture: a call inside a capture never
+ * allocates and fails with HTH_E_INVALID if the workspace is too small).
+ * Batches whose strings total more than about 2^20 * 128 * 8^5 executions
+ * (far beyond device memory unless strings overlap) are flagged by the
+ * device and produce no output; hth_batch_check reports it.
+ * Errors: HTH_E_INVALID (null seed/pointers with count > 0, bad out_width),
+ * HTH_E_OOM, HTH_E_HIP.  count == 0 enqueues nothing. */
+hth_status hth_hash_batch(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
+                          const uint64_t *lengths, uint64_t count, uint8_t *out, uint32_t out_width,
+                          hipStream_t stream);
+
+/* Pre-size the workspace of `stream` for batches of up to max_count strings.
+   Synchronous with respect to the host.  Errors: HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_reserve(uint64_t max_count, hipStream_t stream);
+
+/* Synchronise `stream` and report whether the last batch on it was planned:
+   HTH_OK, or HTH_E_TOO_LARGE if the device rejected its size. */
+hth_status hth_batch_check(hipStream_t stream);
+
+/* Tuning of the batched kernel (defaults are chosen by the library).
+   waves_per_cu: resident single-wave workgroups per compute unit of the
+   persistent grid (0 = occupancy limit).  min_task_level: tasks cover at least
+   128 * 8^min_task_level executions (0..5).  Applies to later calls. */
+hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

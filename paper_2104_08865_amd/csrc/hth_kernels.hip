@@ -1,0 +1,679 @@
+// HalftimeHash kernels for gfx950 (MI355X).
+//
+// One launch hashes a whole batch of strings.  Work is cut into tasks: a task
+// is an aligned range of T = 128 * 8^j full EHC executions of one string (the
+// last task of a string also takes its tail, its length term and any partial
+// range).  A persistent grid of single-wave workgroups pulls tasks from a
+// device counter.
+//
+// Inside a task a wave works in passes of 128 executions.  Lane l = 4q + r
+// (q = 0..15, r = 0..3) owns instances 2r and 2r+1 (the two 64-bit words of a
+// 16-byte load inside each 64-byte block, paper §2: instance j = word j of
+// every block) of the 8 consecutive executions p + 8q .. p + 8q + 7.  For each
+// execution it loads the d*w blocks with 16-byte loads, runs Encode, Hash and
+// Combine (§3.3, §4, §5.1) in registers, and feeds the k outputs into the
+// first tree level: 8 consecutive executions of a lane form one level-1 node
+// of every tree, so levels 0 and 1 need no data exchange.  Level 2 (64
+// executions) is a 3-step butterfly over lanes q, q^1, q^2, q^4 of each half
+// wave.  Above level 2 a node's value is the sum of one term per child (the
+// NH variant of §3.2: NH of children 0..6 against their position's key plus
+// child 7), so children are folded into their parent by adding their terms:
+// in LDS when the parent lies inside the task, with 64-bit atomics in device
+// memory when it spans tasks (the 8th arrival, found by a counter, carries
+// on with the parent).  Items the stack construction of Eq. (3) leaves over
+// (one per unit of each base-8 digit of the execution count) go straight into
+// the final NH (§5.2).  All of these, the tail (§6.1) and the length term are
+// sums mod 2^64, so their order never changes the result.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hth_family.h"
+#include "hth_kernels.h"
+
+namespace hth {
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+
+// NH of one word (lo, hi) against one key (§3.2): halves added mod 2^32, one
+// 32x32->64 product (v_mad_u64_u32 with the accumulate).
+__device__ __forceinline__ uint64_t nh_acc(uint64_t acc, uint32_t lo, uint32_t hi, uint64_t key) {
+  return acc + (uint64_t)(uint32_t)(lo + (uint32_t)key) * (uint32_t)(hi + (uint32_t)(key >> 32));
+}
+__device__ __forceinline__ uint64_t nh_acc(uint64_t acc, uint64_t x, uint64_t key) {
+  return nh_acc(acc, (uint32_t)x, (uint32_t)(x >> 32), key);
+}
+
+// Multiply by one of the small combine coefficients with shifts and adds.
+__device__ __forceinline__ uint64_t mulc(int c, uint64_t h) {
+  switch (c) {
+    case 0: return 0;
+    case 1: return h;
+    case 2: return h << 1;
+    case 3: return (h << 1) + h;
+    case 4: return h << 2;
+    case 5: return (h << 2) + h;
+    case 6: return (h << 2) + (h << 1);
+    case 7: return (h << 3) - h;
+    case 8: return h << 3;
+    case 9: return (h << 3) + h;
+    default: return h * (uint64_t)c;
+  }
+}
+
+__device__ __forceinline__ uint4 load16(const uint8_t* p) {
+  uint4 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = __shfl((uint32_t)v, src);
+  uint32_t hi = __shfl((uint32_t)(v >> 32), src);
+  return (uint64_t)hi << 32 | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  uint32_t lo = __shfl_xor((uint32_t)v, m);
+  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m);
+  return (uint64_t)hi << 32 | lo;
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += shfl_xor64(v, m);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32 |
+         __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// Number of complete nodes of level l (8^l executions each) among N executions.
+__device__ __forceinline__ uint64_t nodes_at(uint64_t N, int l) { return l >= 22 ? 0 : N >> (3 * l); }
+
+// ---------------------------------------------------------------------------
+// EHC of one execution for the two instances of a lane.
+// ---------------------------------------------------------------------------
+
+template <int WIDTH>
+__device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, const uint64_t* __restrict__ S_ehc,
+                                     uint64_t z0[], uint64_t z1[]) {
+  using Fm = Family<WIDTH>;
+  constexpr int D = Fm::D, K = Fm::K, R = K - 1;
+  uint4 x[D * kSym];
+#pragma unroll
+  for (int i = 0; i < D * kSym; ++i) x[i] = load16(eb + 64 * i);
+
+  uint64_t par0[R > 0 ? R : 1][kSym], par1[R > 0 ? R : 1][kSym];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int u = 0; u < kSym; ++u) par0[r][u] = par1[r][u] = 0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) z0[t] = z1[t] = 0;
+
+  // systematic items: hash each word, and add it into the parity words whose
+  // binary image selects it
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    uint64_t h0 = 0, h1 = 0;
+#pragma unroll
+    for (int v = 0; v < kSym; ++v) {
+      const uint4 w = x[c * kSym + v];
+      const uint64_t key = S_ehc[c * kSym + v];
+      h0 = nh_acc(h0, w.x, w.y, key);
+      h1 = nh_acc(h1, w.z, w.w, key);
+      const uint64_t w0 = (uint64_t)w.y << 32 | w.x, w1 = (uint64_t)w.w << 32 | w.z;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < kSym; ++u)
+          if (image_bit(Fm::P[r][c], u, v)) {
+            par0[r][u] += w0;
+            par1[r][u] += w1;
+          }
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      z0[t] += mulc(Fm::T[t][c], h0);
+      z1[t] += mulc(Fm::T[t][c], h1);
+    }
+  }
+  // parity items
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    uint64_t h0 = 0, h1 = 0;
+#pragma unroll
+    for (int u = 0; u < kSym; ++u) {
+      const uint64_t key = S_ehc[(D + r) * kSym + u];
+      h0 = nh_acc(h0, par0[r][u], key);
+      h1 = nh_acc(h1, par1[r][u], key);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      z0[t] += mulc(Fm::T[t][D + r], h0);
+      z1[t] += mulc(Fm::T[t][D + r], h1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Planning kernels: tasks and cross-task accumulators per string.
+// ---------------------------------------------------------------------------
+
+// Per string and per candidate task size 128 * 8^j: number of tasks, and
+// number of cross-task accumulators (complete nodes of levels >= j + 3).
+__device__ __forceinline__ void plan_counts(uint64_t N, int j, uint64_t& tasks, uint64_t& accs) {
+  const int shift = 7 + 3 * j;
+  tasks = N ? ((N + (1ull << shift) - 1) >> shift) : 1;
+  accs = 0;
+  for (int l = j + 3; l < 22; ++l) accs += nodes_at(N, l);
+}
+
+constexpr int kPlanThreads = 256;
+constexpr int kPlanPer = 4;
+constexpr int kPlanBlock = kPlanThreads * kPlanPer;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* lds, T& total) {
+  // Hillis-Steele over 256 threads; lds holds 256 entries.
+  const int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kPlanThreads; off <<= 1) {
+    T add = tid >= off ? lds[tid - off] : 0;
+    __syncthreads();
+    lds[tid] += add;
+    __syncthreads();
+  }
+  T incl = lds[tid];
+  total = lds[kPlanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
+                                                                  uint64_t count, uint32_t exec_bytes,
+                                                                  uint64_t* __restrict__ block_sums) {
+  __shared__ uint64_t lds[kPlanThreads];
+  const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + threadIdx.x * kPlanPer;
+  uint64_t N[kPlanPer];
+  for (int i = 0; i < kPlanPer; ++i) N[i] = base + i < count ? lengths[base + i] / exec_bytes : 0;
+  for (int j = 0; j < kPlanCandidates; ++j) {
+    uint64_t t = 0, a = 0;
+    for (int i = 0; i < kPlanPer; ++i) {
+      if (base + i >= count) continue;
+      uint64_t ti, ai;
+      plan_counts(N[i], j, ti, ai);
+      t += ti;
+      a += ai;
+    }
+    uint64_t tot_t, tot_a;
+    block_exclusive_scan<uint64_t>(t, lds, tot_t);
+    block_exclusive_scan<uint64_t>(a, lds, tot_a);
+    if (threadIdx.x == 0) {
+      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j] = tot_t;
+      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j + 1] = tot_a;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
+    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
+    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
+    uint32_t min_j, uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start,
+    uint32_t* __restrict__ acc_start, uint32_t* __restrict__ ctl) {
+  __shared__ uint64_t lds[kPlanThreads];
+  __shared__ uint32_t incl[kPlanBlock];
+  __shared__ uint64_t s_choice[3];  // j, task base, acc base
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    // choose the smallest task size whose plan fits the workspace
+    int jsel = -1;
+    for (int j = (int)min_j; j < kPlanCandidates && jsel < 0; ++j) {
+      uint64_t tt = 0, ta = 0;
+      for (uint32_t b = 0; b < nblocks; ++b) {
+        tt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
+        ta += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
+      }
+      if (tt <= cap_tasks && ta <= cap_accs) jsel = j;
+    }
+    uint64_t bt = 0, ba = 0;
+    if (jsel >= 0)
+      for (uint32_t b = 0; b < blockIdx.x; ++b) {
+        bt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
+        ba += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel + 1];
+      }
+    s_choice[0] = (uint64_t)(int64_t)jsel;
+    s_choice[1] = bt;
+    s_choice[2] = ba;
+    if (blockIdx.x == 0) {
+      uint64_t tt = 0;
+      if (jsel >= 0)
+        for (uint32_t b = 0; b < nblocks; ++b) tt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
+      ctl[kCtlNext] = 0;
+      ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt : 0;
+      ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
+      ctl[kCtlError] = jsel >= 0 ? 0 : 1;
+    }
+  }
+  __syncthreads();
+  const int64_t jsel = (int64_t)s_choice[0];
+  if (jsel < 0) return;
+  const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + tid * kPlanPer;
+  uint64_t tk[kPlanPer], ac[kPlanPer];
+  uint64_t st = 0, sa = 0;
+  for (int i = 0; i < kPlanPer; ++i) {
+    tk[i] = ac[i] = 0;
+    if (base + i < count) plan_counts(lengths[base + i] / exec_bytes, (int)jsel, tk[i], ac[i]);
+    st += tk[i];
+    sa += ac[i];
+  }
+  uint64_t blk_t, blk_a;
+  uint64_t et = block_exclusive_scan<uint64_t>(st, lds, blk_t);
+  uint64_t ea = block_exclusive_scan<uint64_t>(sa, lds, blk_a);
+  uint64_t run_t = s_choice[1] + et, run_a = s_choice[2] + ea;
+  uint64_t loc = et;
+  for (int i = 0; i < kPlanPer; ++i) {
+    if (base + i < count) {
+      task_start[base + i] = (uint32_t)run_t;
+      acc_start[base + i] = (uint32_t)run_a;
+    }
+    run_t += tk[i];
+    run_a += ac[i];
+    loc += tk[i];
+    incl[tid * kPlanPer + i] = (uint32_t)loc;  // inclusive task count inside the block
+  }
+  __syncthreads();
+  // fill the task -> string table for the tasks of this block's strings
+  const uint64_t first = (uint64_t)blockIdx.x * kPlanBlock;
+  const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
+  for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
+    int lo = 0, hi = nstr - 1;  // first string whose inclusive count exceeds e
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if ((uint64_t)incl[mid] > e) hi = mid;
+      else lo = mid + 1;
+    }
+    task_string[s_choice[1] + e] = (uint32_t)(first + lo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Main kernel.
+// ---------------------------------------------------------------------------
+
+// Local accumulators for parents inside a task: levels 3 .. 3 + kMaxLocal - 1.
+constexpr int kMaxLocal = kPlanCandidates;
+
+template <int WIDTH>
+struct Ctx {
+  static constexpr int K = Family<WIDTH>::K;
+  const uint64_t* __restrict__ ent;
+  uint64_t N;
+  uint32_t j;  // task size 128 * 8^j executions
+  uint64_t acc_base;
+  uint64_t* gacc;
+  uint32_t* gcnt;
+};
+
+// Offset of the accumulator of node `parent` at level l among one string's
+// cross-task accumulators (levels j + 3 and up, complete nodes only).
+__device__ __forceinline__ uint64_t acc_index(uint64_t N, uint32_t j, int l, uint64_t parent) {
+  uint64_t off = 0;
+  for (int m = (int)j + 3; m < l; ++m) off += nodes_at(N, m);
+  return off + parent;
+}
+
+// Fold one complete node of level l (index n within the string), held by
+// lanes 0..3 (instances 2r, 2r+1 of every tree), into the tree above it.
+// Called by the whole wave; all control flow is wave-uniform.
+template <int WIDTH>
+__device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], uint64_t v1[], uint64_t F[],
+                        uint64_t (*lacc)[Family<WIDTH>::K][kBlock]) {
+  constexpr int K = Family<WIDTH>::K;
+  using Ly = Layout<WIDTH>;
+  const int lane = threadIdx.x;
+  const bool owner = lane < 4;
+  const int j0 = 2 * lane, j1 = 2 * lane + 1;
+  for (;;) {
+    const uint64_t parent = n >> 3;
+    const int pos = (int)(n & 7);
+    if (parent >= nodes_at(c.N, l + 1)) {
+      // the parent is incomplete: this node is a leftover item (l, pos)
+      if (owner) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + l) * (kFan - 1) + pos) * kBlock;
+          F[t] = nh_acc(F[t], v0[t], kf[j0]);
+          F[t] = nh_acc(F[t], v1[t], kf[j1]);
+        }
+      }
+      return;
+    }
+    uint64_t term0[K], term1[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      if (pos < kFan - 1) {
+        const uint64_t key = c.ent[Ly::tree + (t * kLevels + l) * (kFan - 1) + pos];
+        term0[t] = nh_acc(0, v0[t], key);
+        term1[t] = nh_acc(0, v1[t], key);
+      } else {
+        term0[t] = v0[t];
+        term1[t] = v1[t];
+      }
+    }
+    if (l + 1 <= (int)c.j + 2) {
+      // parent inside the task: children arrive in order
+      const int li = l + 1 - 3;
+      if (owner) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          lacc[li][t][j0] += term0[t];
+          lacc[li][t][j1] += term1[t];
+        }
+      }
+      if (pos != kFan - 1) return;
+      if (owner) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          v0[t] = lacc[li][t][j0];
+          v1[t] = lacc[li][t][j1];
+          lacc[li][t][j0] = 0;
+          lacc[li][t][j1] = 0;
+        }
+      }
+      ++l;
+      n = parent;
+      continue;
+    }
+    // parent spans tasks: add the terms to its device accumulator
+    const uint64_t idx = c.acc_base + acc_index(c.N, c.j, l + 1, parent);
+    uint64_t* acc = c.gacc + idx * (uint64_t)(kMaxK * kBlock);
+    if (owner) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        __hip_atomic_fetch_add(acc + t * kBlock + j0, term0[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(acc + t * kBlock + j1, term1[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __threadfence();
+    __builtin_amdgcn_wave_barrier();
+    uint32_t old = 0;
+    if (lane == 0)
+      old = __hip_atomic_fetch_add(c.gcnt + idx, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    old = uniform(old);
+    if (old != kFan - 1) return;
+    // the 8th child: the parent is complete; read and clear its accumulator
+    // and counter (they stay zero for the next launch)
+    __threadfence();
+    if (owner) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        v0[t] = __hip_atomic_exchange(acc + t * kBlock + j0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v1[t] = __hip_atomic_exchange(acc + t * kBlock + j1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __hip_atomic_store(c.gcnt + idx, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_wave_barrier();
+    ++l;
+    n = parent;
+  }
+}
+
+template <int WIDTH>
+__global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
+  using Fm = Family<WIDTH>;
+  using Ly = Layout<WIDTH>;
+  constexpr int K = Fm::K;
+  constexpr uint64_t XB = Ly::exec_bytes;
+  __shared__ uint64_t lacc[kMaxLocal][K][kBlock];
+
+  const int lane = threadIdx.x;
+  const int q = lane >> 2, r = lane & 3;
+  const uint32_t total = uniform(a.ctl[kCtlTotal]);
+  const uint32_t jlev = uniform(a.ctl[kCtlLevel]);
+  const uint64_t texec = 128ull << (3 * jlev);
+  const uint64_t* __restrict__ ent = a.ent;
+
+  // each owner lane (0..3) only ever touches its own two instances' slots
+  if (lane < 4) {
+    for (int li = 0; li < kMaxLocal; ++li)
+#pragma unroll
+      for (int t = 0; t < K; ++t) lacc[li][t][2 * lane] = lacc[li][t][2 * lane + 1] = 0;
+  }
+
+  for (;;) {
+    __builtin_amdgcn_wave_barrier();
+    uint32_t task = 0;
+    if (lane == 0) task = atomicAdd(a.ctl + kCtlNext, 1u);
+    task = uniform(task);
+    if (task >= total) break;
+    const uint32_t s = uniform(a.task_string[task]);
+    const uint64_t tau = task - uniform(a.task_start[s]);
+    const uint64_t off = uniform64(a.offsets[s]);
+    const uint64_t L = uniform64(a.lengths[s]);
+    const uint64_t N = L / XB;
+    const uint64_t ntask = N ? (N + texec - 1) / texec : 1;
+    const uint8_t* __restrict__ str = a.bytes + off;
+
+    Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)uniform(a.acc_start[s]) : 0, a.gacc, a.gcnt};
+    uint64_t F[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = 0;
+
+    const uint64_t g0 = tau * texec;
+    const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
+    for (uint64_t p = g0; p < g1; p += 128) {
+      const uint64_t nv = N - p < 128 ? N - p : 128;
+      const int64_t cnt64 = (int64_t)nv - 8 * q;
+      const int cnt = cnt64 < 0 ? 0 : (cnt64 > 8 ? 8 : (int)cnt64);
+      uint64_t a0[K], a1[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
+      const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
+      for (int e = 0; e < 8; ++e) {
+        if (e < cnt) {
+          uint64_t z0[K], z1[K];
+          ehc2<WIDTH>(col + e * XB, ent + Ly::ehc, z0, z1);
+          if (cnt == 8) {
+            // level 0 of every tree: child e of this lane's level-1 node
+            if (e < kFan - 1) {
+#pragma unroll
+              for (int t = 0; t < K; ++t) {
+                const uint64_t key = ent[Ly::tree + (t * kLevels) * (kFan - 1) + e];
+                a0[t] = nh_acc(a0[t], z0[t], key);
+                a1[t] = nh_acc(a1[t], z1[t], key);
+              }
+            } else {
+#pragma unroll
+              for (int t = 0; t < K; ++t) {
+                a0[t] += z0[t];
+                a1[t] += z1[t];
+              }
+            }
+          } else {
+            // incomplete level-1 node: these leaves are level-0 leftovers
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+              const uint64_t* kf = ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + e) * kBlock;
+              F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
+              F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
+            }
+          }
+        }
+      }
+      // level 1 -> level 2: this lane holds level-1 node 8 * (p/64) + q
+      // (for every tree and its two instances) when its column is complete.
+      const bool half_full = (q < 8) ? nv >= 64 : nv >= 128;
+      const int pos1 = q & 7;
+      if (cnt == 8 && !half_full) {
+        // complete level-1 node in an incomplete level-2 group: leftover (1, pos1)
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t* kf = ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + pos1) * kBlock;
+          F[t] = nh_acc(F[t], a0[t], kf[2 * r]);
+          F[t] = nh_acc(F[t], a1[t], kf[2 * r + 1]);
+        }
+      }
+      uint64_t n0[K], n1[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        uint64_t t0 = 0, t1 = 0;
+        if (half_full) {
+          if (pos1 < kFan - 1) {
+            const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
+            t0 = nh_acc(0, a0[t], key);
+            t1 = nh_acc(0, a1[t], key);
+          } else {
+            t0 = a0[t];
+            t1 = a1[t];
+          }
+        }
+        t0 += shfl_xor64(t0, 4);
+        t1 += shfl_xor64(t1, 4);
+        t0 += shfl_xor64(t0, 8);
+        t1 += shfl_xor64(t1, 8);
+        t0 += shfl_xor64(t0, 16);
+        t1 += shfl_xor64(t1, 16);
+        n0[t] = t0;
+        n1[t] = t1;
+      }
+      // lanes 0..3 hold level-2 node A (executions p .. p+63), lanes 32..35
+      // node B (p+64 .. p+127)
+      const uint64_t nA = p >> 6;
+      uint64_t b0[K], b1[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        b0[t] = shfl64(n0[t], (lane & 3) + 32);
+        b1[t] = shfl64(n1[t], (lane & 3) + 32);
+      }
+      if (nv >= 64) fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
+      if (nv >= 128) fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
+    }
+
+    if (tau == ntask - 1) {
+      // tail (§6.1): words m0 .. m0+R-1, output t keyed by S_tail[t + m]
+      const uint64_t tb = N * XB;
+      const uint64_t rem = L - tb;
+      const uint64_t R = (rem + 7) / 8;
+      for (uint64_t m = lane; m < R; m += 64) {
+        uint64_t w = 0;
+        const uint8_t* pw = str + tb + 8 * m;
+        if (8 * m + 8 <= rem) {
+          __builtin_memcpy(&w, pw, 8);
+        } else {
+          for (uint64_t b = 0; b < rem - 8 * m; ++b) w |= (uint64_t)pw[b] << (8 * b);
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ent[Ly::len + t]);
+      }
+    }
+
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = wave_sum64(F[t]);
+
+    uint8_t* o = a.out + (uint64_t)s * WIDTH;
+    if (ntask == 1) {
+      if (lane < K) {
+        uint64_t v = F[0];
+#pragma unroll
+        for (int t = 1; t < K; ++t)
+          if (lane == t) v = F[t];
+        __builtin_memcpy(o + 8 * lane, &v, 8);
+      }
+    } else {
+      uint64_t* sacc = a.sacc + (uint64_t)s * kMaxK;
+      if (lane < K) {
+        uint64_t v = F[0];
+#pragma unroll
+        for (int t = 1; t < K; ++t)
+          if (lane == t) v = F[t];
+        __hip_atomic_fetch_add(sacc + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __threadfence();
+      __builtin_amdgcn_wave_barrier();
+      uint32_t old = 0;
+      if (lane == 0)
+        old = __hip_atomic_fetch_add(a.sdone + s, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      old = uniform(old);
+      if (old == ntask - 1) {
+        // last task of the string: read and clear the sums and the counter
+        __threadfence();
+        if (lane < K) {
+          uint64_t v = __hip_atomic_exchange(sacc + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_memcpy(o + 8 * lane, &v, 8);
+          __hip_atomic_store(a.sdone + s, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    // every lane finishes the task here, before the next one is fetched
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+
+template <int WIDTH>
+static const void* main_fn() {
+  return reinterpret_cast<const void*>(&hash_main_kernel<WIDTH>);
+}
+
+const void* main_kernel_fn(uint32_t width) {
+  switch (width) {
+    case 16: return main_fn<16>();
+    case 24: return main_fn<24>();
+    case 32: return main_fn<32>();
+    case 40: return main_fn<40>();
+  }
+  return nullptr;
+}
+
+uint32_t exec_bytes_of(uint32_t width) {
+  switch (width) {
+    case 16: return Layout<16>::exec_bytes;
+    case 24: return Layout<24>::exec_bytes;
+    case 32: return Layout<32>::exec_bytes;
+    case 40: return Layout<40>::exec_bytes;
+  }
+  return 0;
+}
+
+int64_t entropy_offset_of(uint32_t width) { return width_offset((int)width); }
+uint64_t entropy_words_total() { return kEntropyWords; }
+
+hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
+  const uint32_t nblocks = (uint32_t)((p.count + kPlanBlock - 1) / kPlanBlock);
+  hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
+                     p.exec_bytes, p.block_sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
+                     p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.task_string,
+                     p.task_start, p.acc_start, p.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream) {
+  switch (width) {
+    case 16: hipLaunchKernelGGL(hash_main_kernel<16>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 24: hipLaunchKernelGGL(hash_main_kernel<24>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 32: hipLaunchKernelGGL(hash_main_kernel<32>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 40: hipLaunchKernelGGL(hash_main_kernel<40>, dim3(grid), dim3(64), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+uint64_t plan_block_count(uint64_t count) { return (count + kPlanBlock - 1) / kPlanBlock; }
+
+}  // namespace hth

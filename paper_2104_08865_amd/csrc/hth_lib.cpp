@@ -1,0 +1,348 @@
+// libhth host side: the C ABI of include/hth.h, seed objects, per-stream
+// workspaces and launch configuration.  All hashing arithmetic runs in the
+// HIP kernels of hth_kernels.hip; this file only moves arguments, memory and
+// launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hth.h"
+#include "hth_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hth_status fail(hth_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+hth_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? HTH_E_OOM : HTH_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool width_ok(uint32_t w) { return w == 16 || w == 24 || w == 32 || w == 40; }
+int width_index(uint32_t w) { return (int)(w / 8) - 2; }
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014).
+void splitmix64_fill(uint64_t state, uint64_t* out, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    out[i] = z ^ (z >> 31);
+  }
+}
+
+// Workspace of one (device, stream): planning arrays and the cross-task
+// accumulators.  sacc, sdone, gacc and gcnt hold zeros between launches (the
+// kernel that consumes an accumulator resets it), so a workspace is cleared
+// only once, when it is allocated.
+struct Workspace {
+  uint64_t cap_count = 0, cap_tasks = 0, cap_accs = 0, cap_blocks = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  uint32_t* ctl = nullptr;
+  uint64_t* block_sums = nullptr;
+  uint32_t* task_string = nullptr;
+  uint32_t* task_start = nullptr;
+  uint32_t* acc_start = nullptr;
+  uint64_t* sacc = nullptr;
+  uint32_t* sdone = nullptr;
+  uint64_t* gacc = nullptr;
+  uint32_t* gcnt = nullptr;
+};
+
+struct Tuning {
+  uint32_t waves_per_cu = 0;
+  uint32_t min_j = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+Tuning g_tune[4];
+std::map<std::pair<int, int>, uint32_t> g_grid;  // (device, width index) -> persistent grid
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
+  Workspace n;
+  n.cap_count = count < 1024 ? 1024 : count + count / 4;
+  n.cap_tasks = n.cap_count + (1ull << 19);
+  if (n.cap_tasks > (1ull << 31)) n.cap_tasks = 1ull << 31;
+  n.cap_accs = n.cap_tasks * 3 / 10 + 1024;
+  n.cap_blocks = hth::plan_block_count(n.cap_count);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  size_t o_ctl = take(hth::kCtlWords * 4);
+  size_t o_bs = take(n.cap_blocks * 2 * hth::kPlanCandidates * 8);
+  size_t o_ts = take(n.cap_tasks * 4);
+  size_t o_st = take(n.cap_count * 4);
+  size_t o_as = take(n.cap_count * 4);
+  size_t o_sacc = take(n.cap_count * hth::kMaxK * 8);
+  size_t o_sdone = take(n.cap_count * 4);
+  size_t o_gacc = take(n.cap_accs * hth::kMaxK * 8 * 8);
+  size_t o_gcnt = take(n.cap_accs * 4);
+  n.bytes = off;
+  hipError_t e = hipMalloc(&n.mem, n.bytes);
+  if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+  e = hipMemsetAsync(n.mem, 0, n.bytes, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(n.mem);
+    return hip_fail(e, "workspace clear");
+  }
+  char* b = static_cast<char*>(n.mem);
+  n.ctl = reinterpret_cast<uint32_t*>(b + o_ctl);
+  n.block_sums = reinterpret_cast<uint64_t*>(b + o_bs);
+  n.task_string = reinterpret_cast<uint32_t*>(b + o_ts);
+  n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
+  n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
+  n.sacc = reinterpret_cast<uint64_t*>(b + o_sacc);
+  n.sdone = reinterpret_cast<uint32_t*>(b + o_sdone);
+  n.gacc = reinterpret_cast<uint64_t*>(b + o_gacc);
+  n.gcnt = reinterpret_cast<uint32_t*>(b + o_gcnt);
+  if (w.mem) {
+    // the old workspace may still be in use by work queued on this stream
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      (void)hipFree(n.mem);
+      return hip_fail(e, "stream synchronise before workspace growth");
+    }
+    (void)hipFree(w.mem);
+  }
+  w = n;
+  return HTH_OK;
+}
+
+// Workspace for (current device, stream) with room for `count` strings.
+hth_status get_ws(uint64_t count, hipStream_t stream, Workspace** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, stream}];
+  if (!w.mem || w.cap_count < count) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(HTH_E_INVALID,
+                  "workspace for %llu strings must be reserved (hth_reserve) before stream capture",
+                  (unsigned long long)count);
+    hth_status st = ws_alloc(w, count, stream);
+    if (st != HTH_OK) return st;
+  }
+  *out = &w;
+  return HTH_OK;
+}
+
+hth_status grid_for(uint32_t width, uint32_t* grid) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int wi = width_index(width);
+  auto it = g_grid.find({dev, wi});
+  if (it != g_grid.end()) {
+    *grid = it->second;
+    return HTH_OK;
+  }
+  int cus = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device attribute");
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::main_kernel_fn(width), 64, 0);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  uint32_t wpc = per_cu > 0 ? (uint32_t)per_cu : 1;
+  if (g_tune[wi].waves_per_cu && g_tune[wi].waves_per_cu < wpc) wpc = g_tune[wi].waves_per_cu;
+  *grid = (uint32_t)cus * wpc;
+  g_grid[{dev, wi}] = *grid;
+  return HTH_OK;
+}
+
+}  // namespace
+
+struct hth_seed {
+  int device = 0;
+  uint64_t* d_words = nullptr;
+  std::vector<uint64_t> host;
+};
+
+extern "C" {
+
+const char* hth_last_error(void) { return g_err.c_str(); }
+
+size_t hth_entropy_words(void) { return (size_t)hth::entropy_words_total(); }
+
+hth_status hth_seed_from_entropy(const uint64_t* words, size_t n_words, hth_seed** out, hipStream_t stream) {
+  if (!out) return fail(HTH_E_INVALID, "hth_seed_from_entropy: out is null");
+  *out = nullptr;
+  if (!words) return fail(HTH_E_INVALID, "hth_seed_from_entropy: words is null");
+  if (n_words != hth_entropy_words())
+    return fail(HTH_E_INVALID, "hth_seed_from_entropy: n_words is %zu, expected %zu", n_words,
+                hth_entropy_words());
+  hth_seed* s = new (std::nothrow) hth_seed;
+  if (!s) return fail(HTH_E_OOM, "hth_seed_from_entropy: host allocation");
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipGetDevice");
+  }
+  s->host.assign(words, words + n_words);
+  e = hipMalloc(&s->d_words, n_words * 8);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "seed allocation");
+  }
+  // the copy reads s->host, which lives as long as the seed
+  e = hipMemcpyAsync(s->d_words, s->host.data(), n_words * 8, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    (void)hipFree(s->d_words);
+    delete s;
+    return hip_fail(e, "seed upload");
+  }
+  *out = s;
+  return HTH_OK;
+}
+
+hth_status hth_expand_seed(uint64_t user_seed, hth_seed** out, hipStream_t stream) {
+  if (!out) return fail(HTH_E_INVALID, "hth_expand_seed: out is null");
+  std::vector<uint64_t> w(hth_entropy_words());
+  splitmix64_fill(user_seed, w.data(), w.size());
+  return hth_seed_from_entropy(w.data(), w.size(), out, stream);
+}
+
+hth_status hth_seed_entropy(const hth_seed* seed, uint64_t* host_words, size_t n_words) {
+  if (!seed || !host_words) return fail(HTH_E_INVALID, "hth_seed_entropy: null pointer");
+  if (n_words != seed->host.size()) return fail(HTH_E_INVALID, "hth_seed_entropy: n_words mismatch");
+  hipError_t e = hipMemcpy(host_words, seed->d_words, n_words * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "seed download");
+  return HTH_OK;
+}
+
+hth_status hth_seed_free(hth_seed* seed) {
+  if (!seed) return HTH_OK;
+  hipError_t e = hipFree(seed->d_words);
+  delete seed;
+  if (e != hipSuccess) return hip_fail(e, "seed free");
+  return HTH_OK;
+}
+
+hth_status hth_reserve(uint64_t max_count, hipStream_t stream) {
+  Workspace* w = nullptr;
+  return get_ws(max_count ? max_count : 1, stream, &w);
+}
+
+hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level) {
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_set_tuning: out_width %u", out_width);
+  if (min_task_level >= (uint32_t)hth::kPlanCandidates)
+    return fail(HTH_E_INVALID, "hth_set_tuning: min_task_level %u", min_task_level);
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int wi = width_index(out_width);
+  g_tune[wi].waves_per_cu = waves_per_cu;
+  g_tune[wi].min_j = min_task_level;
+  for (auto it = g_grid.begin(); it != g_grid.end();) {
+    if (it->first.second == wi) it = g_grid.erase(it);
+    else ++it;
+  }
+  return HTH_OK;
+}
+
+hth_status hth_hash_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width,
+                          hipStream_t stream) {
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_hash_batch: out_width %u is not 16/24/32/40", out_width);
+  if (!seed) return fail(HTH_E_INVALID, "hth_hash_batch: seed is null");
+  if (count == 0) return HTH_OK;
+  if (!bytes || !offsets || !lengths || !out) return fail(HTH_E_INVALID, "hth_hash_batch: null pointer");
+  if (count > (1ull << 31)) return fail(HTH_E_INVALID, "hth_hash_batch: count %llu exceeds 2^31", (unsigned long long)count);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != seed->device) return fail(HTH_E_INVALID, "hth_hash_batch: seed lives on device %d, current is %d", seed->device, dev);
+
+  Workspace* w = nullptr;
+  hth_status st = get_ws(count, stream, &w);
+  if (st != HTH_OK) return st;
+  uint32_t grid = 0;
+  st = grid_for(out_width, &grid);
+  if (st != HTH_OK) return st;
+  uint32_t min_j;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    min_j = g_tune[width_index(out_width)].min_j;
+  }
+
+  hth::PlanArgs p{};
+  p.lengths = lengths;
+  p.count = count;
+  p.exec_bytes = hth::exec_bytes_of(out_width);
+  p.block_sums = w->block_sums;
+  p.cap_tasks = w->cap_tasks;
+  p.cap_accs = w->cap_accs;
+  p.min_j = min_j;
+  p.task_string = w->task_string;
+  p.task_start = w->task_start;
+  p.acc_start = w->acc_start;
+  p.ctl = w->ctl;
+  e = hth::launch_plan(p, stream);
+  if (e != hipSuccess) return hip_fail(e, "plan launch");
+
+  hth::MainArgs a{};
+  a.bytes = bytes;
+  a.offsets = offsets;
+  a.lengths = lengths;
+  a.out = out;
+  a.ent = seed->d_words + hth::entropy_offset_of(out_width);
+  a.task_string = w->task_string;
+  a.task_start = w->task_start;
+  a.acc_start = w->acc_start;
+  a.sacc = w->sacc;
+  a.sdone = w->sdone;
+  a.gacc = w->gacc;
+  a.gcnt = w->gcnt;
+  a.ctl = w->ctl;
+  e = hth::launch_main(out_width, a, grid, stream);
+  if (e != hipSuccess) return hip_fail(e, "main launch");
+  return HTH_OK;
+}
+
+hth_status hth_batch_check(hipStream_t stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  uint32_t* ctl = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find({dev, stream});
+    if (it == g_ws.end()) return HTH_OK;
+    ctl = it->second.ctl;
+  }
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+  uint32_t err = 0;
+  e = hipMemcpy(&err, ctl + hth::kCtlError, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  if (err) return fail(HTH_E_TOO_LARGE, "the last batch on this stream exceeded the workspace plan limits");
+  return HTH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""Python binding of libhth (argument marshalling only).
+
+Every step of the hash runs in the HIP kernels of libhth.so; this module
+only loads the library, converts torch tensors to pointers and passes the
+current torch stream.  It raises if the library has not been built (there is
+no fallback path).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhth.so")
+
+HTH_OK = 0
+HTH_E_INVALID = -1
+HTH_E_OOM = -2
+HTH_E_HIP = -3
+HTH_E_BUSY = -4
+HTH_E_TOO_LARGE = -5
+
+WIDTHS = (16, 24, 32, 40)
+
+# Exported symbols declared in include/hth.h (checked by the CPU test suite).
+SYMBOLS = (
+    "hth_last_error", "hth_entropy_words", "hth_expand_seed", "hth_seed_from_entropy",
+    "hth_seed_entropy", "hth_seed_free", "hth_hash_batch", "hth_reserve", "hth_batch_check",
+    "hth_set_tuning",
+)
+
+_lib = None
+
+
+class HthError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libhth error {status}: {message}")
+        self.status = status
+
+
+def lib():
+    """Load libhth.so (built by paper_2104_08865_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_08865_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        u64 = ctypes.c_uint64
+        u32 = ctypes.c_uint32
+        L.hth_last_error.restype = ctypes.c_char_p
+        L.hth_entropy_words.restype = ctypes.c_size_t
+        L.hth_expand_seed.argtypes = [u64, ctypes.POINTER(vp), vp]
+        L.hth_seed_from_entropy.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(vp), vp]
+        L.hth_seed_entropy.argtypes = [vp, vp, ctypes.c_size_t]
+        L.hth_seed_free.argtypes = [vp]
+        L.hth_hash_batch.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp]
+        L.hth_reserve.argtypes = [u64, vp]
+        L.hth_batch_check.argtypes = [vp]
+        L.hth_set_tuning.argtypes = [u32, u32, u32]
+        for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
+                     "hth_hash_batch", "hth_reserve", "hth_batch_check", "hth_set_tuning"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HTH_OK:
+        raise HthError(rc, lib().hth_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def entropy_words():
+    return int(lib().hth_entropy_words())
+
+
+class Seed:
+    """A device-resident seed (the family member's entropy words)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def entropy(self):
+        out = np.zeros(entropy_words(), dtype=np.uint64)
+        _check(lib().hth_seed_entropy(self._h, out.ctypes.data, out.size))
+        return out
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            lib().hth_seed_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def expand_seed(user_seed, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().hth_expand_seed(ctypes.c_uint64(user_seed & (2**64 - 1)), ctypes.byref(h), _stream(stream)))
+    return Seed(h)
+
+
+def seed_from_entropy(words, stream=None):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    h = ctypes.c_void_p()
+    _check(lib().hth_seed_from_entropy(w.ctypes.data, w.size, ctypes.byref(h), _stream(stream)))
+    # the upload reads host memory owned by the library; nothing to keep here
+    return Seed(h)
+
+
+def reserve(max_count, stream=None):
+    _check(lib().hth_reserve(max_count, _stream(stream)))
+
+
+def set_tuning(out_width, waves_per_cu=0, min_task_level=0):
+    _check(lib().hth_set_tuning(out_width, waves_per_cu, min_task_level))
+
+
+def batch_check(stream=None):
+    _check(lib().hth_batch_check(_stream(stream)))
+
+
+def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None):
+    """Hash strings data[offsets[i] : offsets[i] + lengths[i]] on the GPU.
+
+    data: uint8 CUDA tensor; offsets, lengths: int64 CUDA tensors (read as
+    unsigned); returns (count, out_width) uint8 CUDA tensor."""
+    import torch
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 CUDA tensor")
+    for t in (offsets, lengths):
+        if t.dtype not in (torch.int64, torch.uint64) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("offsets and lengths must be contiguous int64 CUDA tensors")
+    count = offsets.numel()
+    if lengths.numel() != count:
+        raise ValueError("offsets and lengths differ in size")
+    if out is None:
+        out = torch.empty((count, out_width), dtype=torch.uint8, device=data.device)
+    dp = data.data_ptr() if data.numel() else offsets.data_ptr()
+    _check(lib().hth_hash_batch(seed.handle, ctypes.c_void_p(dp), ctypes.c_void_p(offsets.data_ptr()),
+                                ctypes.c_void_p(lengths.data_ptr()), count, ctypes.c_void_p(out.data_ptr()),
+                                out_width, _stream(stream)))
+    return out

@@ -55,10 +55,13 @@ def random_bytes(seed, nbytes, start_byte=0):
         return np.zeros(0, dtype=np.uint8)
     w0 = start_byte // 8
     w1 = (start_byte + nbytes + 7) // 8
-    words = splitmix64(seed, w1 - w0, start=w0)
-    raw = words.astype("<u8").view(np.uint8)
+    raw = np.empty((w1 - w0) * 8, dtype=np.uint8)
+    step = 1 << 22
+    for a in range(w0, w1, step):
+        n = min(step, w1 - a)
+        raw[(a - w0) * 8:(a - w0 + n) * 8] = splitmix64(seed, n, start=a).astype("<u8").view(np.uint8)
     off = start_byte - 8 * w0
-    return raw[off:off + nbytes].copy()
+    return raw[off:off + nbytes]
 
 
 def _signed(c):

@@ -1,0 +1,76 @@
+"""The C ABI library loads, exports every symbol include/hth.h declares, and
+rejects bad host-side arguments before touching the GPU.  No compute calls."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hth.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hth_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2104_08865_amd import hth
+    if not os.path.exists(hth.LIB_PATH):
+        from paper_2104_08865_amd import build
+        build.build()
+    return hth.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("hth_expand_seed", "hth_hash_batch", "hth_seed_free", "hth_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2104_08865_amd import hth
+    out = subprocess.run(["nm", "-D", "--defined-only", hth.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (hth_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    assert set(hth.SYMBOLS) <= exported
+
+
+def test_entropy_words(lib):
+    assert lib.hth_entropy_words() == 2688 + 3980 + 5245 + 6456
+
+
+def test_host_side_rejections(lib):
+    from paper_2104_08865_amd import hth
+    p = ctypes.c_void_p(1)
+    rc = lib.hth_hash_batch(p, p, p, p, 1, p, 17, None)
+    assert rc == hth.HTH_E_INVALID and b"out_width" in lib.hth_last_error()
+    rc = lib.hth_hash_batch(None, p, p, p, 1, p, 16, None)
+    assert rc == hth.HTH_E_INVALID and b"seed" in lib.hth_last_error()
+    assert lib.hth_set_tuning(20, 0, 0) == hth.HTH_E_INVALID
+    assert lib.hth_set_tuning(16, 0, 9) == hth.HTH_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.hth_seed_from_entropy(None, 18369, ctypes.byref(h), None) == hth.HTH_E_INVALID
+    assert lib.hth_expand_seed(1, None, None) == hth.HTH_E_INVALID
+    assert lib.hth_seed_free(None) == hth.HTH_OK
+
+
+def test_gpu_path_does_not_touch_the_oracle():
+    """The product package never imports, links or loads the oracle, and the
+    oracle never includes the product's sources."""
+    pkg = os.path.join(ROOT, "paper_2104_08865_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b|hth_ref_|libhth_ref|hth_oracle", text, re.M), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".c", ".h", ".py")):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert not re.search(r'^\s*(import|from)\s+paper_2104_08865_amd|^\s*#\s*include\s*[<"][^>"]*(hth_family|hth_kernels|hth\.h)',
+                                 text, re.M), f

@@ -1,0 +1,210 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer hashing leaves no room for tolerance: every output byte must match.
+Inputs come from the seeded generators in paper_2104_08865_amd.workloads.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2104_08865_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (16, 24, 32, 40)
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def env(oracle_lib):
+    import torch
+    from paper_2104_08865_amd import hth
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.init()
+    seed = hth.expand_seed(1)
+    torch.cuda.synchronize()
+    return {"torch": torch, "hth": hth, "seed": seed, "ent": oracle_lib.expand_seed(1), "oracle": oracle_lib}
+
+
+def _gpu_hash(env, data_np, offs, lens, width, seed=None):
+    torch = env["torch"]
+    d = torch.from_numpy(np.ascontiguousarray(data_np)).cuda() if data_np.size else torch.zeros(1, dtype=torch.uint8, device="cuda")
+    o = torch.from_numpy(np.asarray(offs, dtype=np.uint64).view(np.int64)).cuda()
+    n = torch.from_numpy(np.asarray(lens, dtype=np.uint64).view(np.int64)).cuda()
+    out = env["hth"].hash_batch(seed or env["seed"], d, o, n, width)
+    env["hth"].batch_check()
+    return out.cpu().numpy()
+
+
+def _check(env, data_np, offs, lens, width, label):
+    print(f"[parity] {label} width={width} strings={len(lens)} bytes={int(np.sum(lens))}", flush=True)
+    g = _gpu_hash(env, data_np, offs, lens, width)
+    c = env["oracle"].hash_batch(env["ent"], data_np, offs, lens, width, nthreads=NTHREADS)
+    bad = np.nonzero((g != c).any(axis=1))[0]
+    assert bad.size == 0, f"{label} width {width}: {bad.size} mismatches, first at string {bad[0]} (len {int(lens[bad[0]])})"
+
+
+def test_seed_expansion_matches_oracle(env):
+    assert (env["seed"].entropy() == env["ent"]).all()
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_small_batch(env, width):
+    """1024 x 1 KiB plus the edge lengths 0, 1, 7, 8, 63, 64 and 1, 8, 64 and
+    512 executions +-1, packed back to back (unaligned starts)."""
+    lens = wl.small_batch_lengths(width)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(1, total)
+    _check(env, data, offs, lens, width, "small batch")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_every_length_to_1400_and_odd_offsets(env, width):
+    lens = np.arange(0, 1401, dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(11, total + 64)
+    _check(env, data, offs + np.uint64(3), lens, width, "lengths 0..1400 at offset 3")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_tree_boundaries(env, width):
+    """Execution counts around pass (128), level-3 (512), task-spanning level-4
+    (4096) boundaries and with every base-8 digit set."""
+    xb = wl.execution_bytes(width)
+    lens = []
+    for n in (63, 64, 65, 127, 128, 129, 511, 512, 513, 1023, 1024, 4095, 4096, 4097, 4096 + 512 + 64 + 8 + 1,
+              2 * 4096 + 7 * 512 + 7 * 64 + 7 * 8 + 7):
+        for extra in (0, 1, xb - 1):
+            lens.append(n * xb + extra)
+    lens = np.array(lens, dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(12, total)
+    _check(env, data, offs, lens, width, "tree boundaries")
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_coarse_tasks_same_result(env, level):
+    """Coarser tasks fold levels 3.. inside one wave instead of across tasks:
+    the values must not change."""
+    hth = env["hth"]
+    width = 24
+    xb = wl.execution_bytes(width)
+    lens = np.array([n * xb + 5 for n in (100, 511, 512, 4097, 70000)] + [10, 0], dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(13, total)
+    try:
+        hth.set_tuning(width, 0, level)
+        _check(env, data, offs, lens, width, f"task level {level}")
+    finally:
+        hth.set_tuning(width, 0, 0)
+
+
+def test_batch_invariance_and_overlap(env):
+    """A string hashes the same alone, in a mix, and when strings overlap."""
+    width = 40
+    data = wl.random_bytes(14, 3_000_000)
+    offs = np.array([0, 5, 1_000_003, 17, 0, 2_999_999], dtype=np.uint64)
+    lens = np.array([2_000_000, 1_000_000, 1_999_997, 123_456, 0, 1], dtype=np.uint64)
+    mix = _gpu_hash(env, data, offs, lens, width)
+    for i in range(lens.size):
+        alone = _gpu_hash(env, data, offs[i:i + 1], lens[i:i + 1], width)
+        assert (alone[0] == mix[i]).all()
+    _check(env, data, offs, lens, width, "overlap")
+
+
+def test_raw_entropy_seed(env):
+    """A seed built from caller entropy (here: all words distinct small
+    integers) gives the oracle's values for that entropy."""
+    hth = env["hth"]
+    words = np.arange(1, hth.entropy_words() + 1, dtype=np.uint64) * np.uint64(0x9E3779B1)
+    seed = hth.seed_from_entropy(words)
+    lens = np.array([0, 9, 5000, 200_000], dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(15, total)
+    for width in WIDTHS:
+        g = _gpu_hash(env, data, offs, lens, width, seed=seed)
+        c = env["oracle"].hash_batch(words, data, offs, lens, width)
+        assert (g == c).all()
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_throughput_batch_sampled(env, width):
+    """The 4096 x 1 MiB batch hashed in one launch (the benchmark's
+    configuration); 64 sampled strings checked against the oracle."""
+    torch, hth = env["torch"], env["hth"]
+    print(f"[parity] 4096 x 1 MiB width={width}", flush=True)
+    n, sz = 4096, 1 << 20
+    data = wl.random_bytes_torch(2, n * sz, "cuda")
+    offs = torch.arange(n, dtype=torch.int64, device="cuda") * sz
+    lens = torch.full((n,), sz, dtype=torch.int64, device="cuda")
+    out = hth.hash_batch(hth.expand_seed(2), data, offs, lens, width)
+    hth.batch_check()
+    out = out.cpu().numpy()
+    ent2 = env["oracle"].expand_seed(2)
+    rng = np.random.default_rng(width)
+    sample = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 62)]))
+    strs = np.stack([wl.random_bytes(2, sz, start_byte=int(i) * sz) for i in sample])
+    ref = env["oracle"].hash_batch(ent2, strs.ravel(), np.arange(sample.size, dtype=np.uint64) * np.uint64(sz),
+                                   np.full(sample.size, sz, dtype=np.uint64), width, nthreads=NTHREADS)
+    assert (out[sample] == ref).all()
+    del data
+    torch.cuda.empty_cache()
+
+
+def test_uneven_batch_full(env):
+    """The uneven batch (200,000 log-uniform lengths 16 B - 256 KiB plus every
+    length 0..520, packed back to back), every string checked."""
+    torch, hth = env["torch"], env["hth"]
+    lens = wl.uneven_lengths(3)
+    offs, total = wl.pack(lens)
+    print(f"[parity] uneven batch strings={lens.size} bytes={total}", flush=True)
+    data = wl.random_bytes(3, total)
+    d = torch.from_numpy(data).cuda()
+    o = torch.from_numpy(offs.view(np.int64)).cuda()
+    n = torch.from_numpy(lens.view(np.int64)).cuda()
+    seed3 = hth.expand_seed(3)
+    out = hth.hash_batch(seed3, d, o, n, 24).cpu().numpy()
+    hth.batch_check()
+    ref = env["oracle"].hash_batch(env["oracle"].expand_seed(3), data, offs, lens, 24, nthreads=NTHREADS)
+    bad = np.nonzero((out != ref).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first string {bad[0]} len {int(lens[bad[0]])}"
+
+
+def test_long_string_oracle_1gib(env):
+    """One 1 GiB string (798,915 HH32 executions: seven base-8 digits, task
+    accumulators up to level 6) against the oracle."""
+    torch, hth = env["torch"], env["hth"]
+    sz = 1 << 30
+    print("[parity] one 1 GiB string, width 32", flush=True)
+    data = wl.random_bytes(4, sz)
+    d = torch.from_numpy(data).cuda()
+    o = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n = torch.full((1,), sz, dtype=torch.int64, device="cuda")
+    seed4 = hth.expand_seed(4)
+    g = hth.hash_batch(seed4, d, o, n, 32).cpu().numpy()
+    ref = env["oracle"].hash_bytes(env["oracle"].expand_seed(4), data, 32)
+    assert (g[0] == ref).all()
+
+
+def test_long_string_8gib_decompositions_agree(env):
+    """The 8 GiB string at full size: the cross-task atomic cascade (tasks of
+    128 executions) and in-wave folding of levels 3 and 4 (tasks of 128 * 8^2
+    executions) give the same value (the oracle itself is checked on the
+    1 GiB string)."""
+    torch, hth = env["torch"], env["hth"]
+    sz = 8 << 30
+    print("[parity] one 8 GiB string, width 32, two decompositions", flush=True)
+    data = wl.random_bytes_torch(4, sz, "cuda")
+    o = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n = torch.full((1,), sz, dtype=torch.int64, device="cuda")
+    seed4 = hth.expand_seed(4)
+    a = hth.hash_batch(seed4, data, o, n, 32).cpu()
+    try:
+        hth.set_tuning(32, 0, 2)
+        b = hth.hash_batch(seed4, data, o, n, 32).cpu()
+    finally:
+        hth.set_tuning(32, 0, 0)
+    assert (a == b).all()
+    del data
+    torch.cuda.empty_cache()
