@@ -114,6 +114,16 @@ hth_status hth_hash_batch(const hth_seed *seed, const uint8_t *bytes, const uint
                           const uint64_t *lengths, uint64_t count, uint8_t *out, uint32_t out_width,
                           hipStream_t stream);
 
+/* hth_hash_batch, and also record `main_start` and `main_stop` (events the
+   caller created with hipEventCreate; either may be null) on `stream`
+   immediately before and after the hashing kernel, so that the caller can
+   time that kernel alone (the planning step runs before main_start).
+   Same arguments, errors and semantics as hth_hash_batch otherwise. */
+hth_status hth_hash_batch_timed(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
+                                const uint64_t *lengths, uint64_t count, uint8_t *out,
+                                uint32_t out_width, hipStream_t stream, hipEvent_t main_start,
+                                hipEvent_t main_stop);
+
 /* Pre-size the workspace of `stream` for batches of up to max_count strings.
    Synchronous with respect to the host.  Errors: HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_reserve(uint64_t max_count, hipStream_t stream);

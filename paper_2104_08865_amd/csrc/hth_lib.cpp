@@ -269,6 +269,12 @@ hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t mi
 hth_status hth_hash_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                           const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width,
                           hipStream_t stream) {
+  return hth_hash_batch_timed(seed, bytes, offsets, lengths, count, out, out_width, stream, nullptr, nullptr);
+}
+
+hth_status hth_hash_batch_timed(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                                const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width,
+                                hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop) {
   if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_hash_batch: out_width %u is not 16/24/32/40", out_width);
   if (!seed) return fail(HTH_E_INVALID, "hth_hash_batch: seed is null");
   if (count == 0) return HTH_OK;
@@ -320,8 +326,10 @@ hth_status hth_hash_batch(const hth_seed* seed, const uint8_t* bytes, const uint
   a.gacc = w->gacc;
   a.gcnt = w->gcnt;
   a.ctl = w->ctl;
+  if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
   e = hth::launch_main(out_width, a, grid, stream);
   if (e != hipSuccess) return hip_fail(e, "main launch");
+  if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;
 }
 

@@ -25,8 +25,8 @@ WIDTHS = (16, 24, 32, 40)
 # Exported symbols declared in include/hth.h (checked by the CPU test suite).
 SYMBOLS = (
     "hth_last_error", "hth_entropy_words", "hth_expand_seed", "hth_seed_from_entropy",
-    "hth_seed_entropy", "hth_seed_free", "hth_hash_batch", "hth_reserve", "hth_batch_check",
-    "hth_set_tuning",
+    "hth_seed_entropy", "hth_seed_free", "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve",
+    "hth_batch_check", "hth_set_tuning",
 )
 
 _lib = None
@@ -55,11 +55,12 @@ def lib():
         L.hth_seed_entropy.argtypes = [vp, vp, ctypes.c_size_t]
         L.hth_seed_free.argtypes = [vp]
         L.hth_hash_batch.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp]
+        L.hth_hash_batch_timed.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp, vp, vp]
         L.hth_reserve.argtypes = [u64, vp]
         L.hth_batch_check.argtypes = [vp]
         L.hth_set_tuning.argtypes = [u32, u32, u32]
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
-                     "hth_hash_batch", "hth_reserve", "hth_batch_check", "hth_set_tuning"):
+                     "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -133,7 +134,38 @@ def batch_check(stream=None):
     _check(lib().hth_batch_check(_stream(stream)))
 
 
-def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None):
+class Timer:
+    """A pair of HIP events (via the HIP runtime) around the hashing kernel."""
+
+    _hip = None
+
+    def __init__(self):
+        if Timer._hip is None:
+            Timer._hip = ctypes.CDLL("libamdhip64.so")
+            Timer._hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+            Timer._hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+            Timer._hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+            Timer._hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.start = ctypes.c_void_p()
+        self.stop = ctypes.c_void_p()
+        if Timer._hip.hipEventCreate(ctypes.byref(self.start)) or Timer._hip.hipEventCreate(ctypes.byref(self.stop)):
+            raise RuntimeError("hipEventCreate failed")
+
+    def elapsed_ms(self):
+        ms = ctypes.c_float()
+        if Timer._hip.hipEventSynchronize(self.stop) or Timer._hip.hipEventElapsedTime(ctypes.byref(ms), self.start, self.stop):
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def __del__(self):
+        try:
+            Timer._hip.hipEventDestroy(self.start)
+            Timer._hip.hipEventDestroy(self.stop)
+        except Exception:
+            pass
+
+
+def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None, timer=None):
     """Hash strings data[offsets[i] : offsets[i] + lengths[i]] on the GPU.
 
     data: uint8 CUDA tensor; offsets, lengths: int64 CUDA tensors (read as
@@ -150,7 +182,10 @@ def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None):
     if out is None:
         out = torch.empty((count, out_width), dtype=torch.uint8, device=data.device)
     dp = data.data_ptr() if data.numel() else offsets.data_ptr()
-    _check(lib().hth_hash_batch(seed.handle, ctypes.c_void_p(dp), ctypes.c_void_p(offsets.data_ptr()),
-                                ctypes.c_void_p(lengths.data_ptr()), count, ctypes.c_void_p(out.data_ptr()),
-                                out_width, _stream(stream)))
+    args = (seed.handle, ctypes.c_void_p(dp), ctypes.c_void_p(offsets.data_ptr()),
+            ctypes.c_void_p(lengths.data_ptr()), count, ctypes.c_void_p(out.data_ptr()), out_width, _stream(stream))
+    if timer is None:
+        _check(lib().hth_hash_batch(*args))
+    else:
+        _check(lib().hth_hash_batch_timed(*args, timer.start, timer.stop))
     return out

@@ -138,7 +138,8 @@ def test_throughput_batch_sampled(env, width):
     data = wl.random_bytes_torch(2, n * sz, "cuda")
     offs = torch.arange(n, dtype=torch.int64, device="cuda") * sz
     lens = torch.full((n,), sz, dtype=torch.int64, device="cuda")
-    out = hth.hash_batch(hth.expand_seed(2), data, offs, lens, width)
+    seed2 = hth.expand_seed(2)
+    out = hth.hash_batch(seed2, data, offs, lens, width)
     hth.batch_check()
     out = out.cpu().numpy()
     ent2 = env["oracle"].expand_seed(2)
@@ -148,6 +149,29 @@ def test_throughput_batch_sampled(env, width):
     ref = env["oracle"].hash_batch(ent2, strs.ravel(), np.arange(sample.size, dtype=np.uint64) * np.uint64(sz),
                                    np.full(sample.size, sz, dtype=np.uint64), width, nthreads=NTHREADS)
     assert (out[sample] == ref).all()
+    del data
+    torch.cuda.empty_cache()
+
+
+def test_offsets_and_lengths_with_bit_31_set(env):
+    """Regression: 64-bit offsets and lengths whose low 32-bit half has bit 31
+    set (a sign-extended half once turned such offsets into wild addresses)."""
+    torch, hth = env["torch"], env["hth"]
+    big = (1 << 31) + (3 << 20)
+    print(f"[parity] offsets/lengths with bit 31 set, buffer {big} bytes", flush=True)
+    data = wl.random_bytes_torch(21, big, "cuda")
+    offs = np.array([(1 << 31) + 3, (1 << 31) - 7, 0, (1 << 31) + (1 << 20)], dtype=np.uint64)
+    lens = np.array([(1 << 20) + 5, 300_000, (1 << 31) + 1000, 77], dtype=np.uint64)
+    o = torch.from_numpy(offs.view(np.int64)).cuda()
+    n = torch.from_numpy(lens.view(np.int64)).cuda()
+    seed = env["seed"]
+    for width in (16, 40):
+        g = hth.hash_batch(seed, data, o, n, width).cpu().numpy()
+        hth.batch_check()
+        for i in range(lens.size):
+            s = wl.random_bytes(21, int(lens[i]), start_byte=int(offs[i]))
+            ref = env["oracle"].hash_bytes(env["ent"], s, width)
+            assert (g[i] == ref).all(), (width, i)
     del data
     torch.cuda.empty_cache()
 
