@@ -132,11 +132,16 @@ hth_status hth_reserve(uint64_t max_count, hipStream_t stream);
    HTH_OK, or HTH_E_TOO_LARGE if the device rejected its size. */
 hth_status hth_batch_check(hipStream_t stream);
 
-/* Tuning of the batched kernel (defaults are chosen by the library).
+/* Tuning of the batched kernel for one output width; applies to later calls.
    waves_per_cu: resident single-wave workgroups per compute unit of the
-   persistent grid (0 = occupancy limit).  min_task_level: tasks cover at least
-   128 * 8^min_task_level executions (0..5).  Applies to later calls. */
-hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level);
+   persistent grid (0 = the occupancy limit, the default).  A task covers
+   128 * 8^j full EHC executions of one string; the planner picks j in
+   [min_task_level, max_task_level] (defaults 0 and 5): the coarsest level that
+   still gives two tasks per resident wave, finer only if the workspace
+   requires.  Setting both levels equal forces one task size.
+   Errors: HTH_E_INVALID (bad width, min > max, max > 5). */
+hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level,
+                          uint32_t max_task_level);
 
 #ifdef __cplusplus
 }

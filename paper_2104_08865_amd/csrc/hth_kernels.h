@@ -18,7 +18,8 @@ struct PlanArgs {
   uint32_t exec_bytes;
   uint64_t* block_sums;  // [nblocks][2 * kPlanCandidates]
   uint64_t cap_tasks, cap_accs;
-  uint32_t min_j;
+  uint32_t min_j, max_j;   // task level range the planner may choose from
+  uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
   uint32_t* task_string;  // [cap_tasks]
   uint32_t* task_start;   // [count]
   uint32_t* acc_start;    // [count]

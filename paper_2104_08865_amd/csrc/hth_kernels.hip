@@ -96,6 +96,18 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return (uint64_t)hi << 32 | lo;
 }
 
+// Cross-task sums live in device memory that only device-scope atomic
+// read-modify-writes ever touch, so they need ordering, not cache
+// maintenance: the workgroup fence keeps the compiler from reordering this
+// wave's atomics, and the wait makes every earlier atomic of the wave
+// complete (performed where all compute units see it) before any later one
+// is issued.  A device-scope fence would also write back and invalidate the
+// L2, which costs far more than the hashing itself.
+__device__ __forceinline__ void complete_atomics() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Number of complete nodes of level l (8^l executions each) among N executions.
 __device__ __forceinline__ uint64_t nodes_at(uint64_t N, int l) { return l >= 22 ? 0 : N >> (3 * l); }
 
@@ -229,23 +241,31 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
 __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
-    uint32_t min_j, uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start,
+    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
+    uint32_t* __restrict__ task_start,
     uint32_t* __restrict__ acc_start, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanThreads];
   __shared__ uint32_t incl[kPlanBlock];
   __shared__ uint64_t s_choice[3];  // j, task base, acc base
   const int tid = threadIdx.x;
   if (tid == 0) {
-    // choose the smallest task size whose plan fits the workspace
-    int jsel = -1;
-    for (int j = (int)min_j; j < kPlanCandidates && jsel < 0; ++j) {
-      uint64_t tt = 0, ta = 0;
+    // Task size: the coarsest level in [min_j, max_j] that still yields
+    // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
+    // grid busy), else min_j; then coarser until the plan fits the workspace.
+    uint64_t tt[kPlanCandidates], ta[kPlanCandidates];
+    for (int j = 0; j < kPlanCandidates; ++j) {
+      tt[j] = ta[j] = 0;
       for (uint32_t b = 0; b < nblocks; ++b) {
-        tt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
-        ta += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
+        tt[j] += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
+        ta[j] += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
       }
-      if (tt <= cap_tasks && ta <= cap_accs) jsel = j;
     }
+    int want = (int)min_j;
+    for (int j = (int)min_j; j <= (int)max_j && j < kPlanCandidates; ++j)
+      if (tt[j] >= target_tasks) want = j;
+    int jsel = -1;
+    for (int j = want; j < kPlanCandidates && jsel < 0; ++j)
+      if (tt[j] <= cap_tasks && ta[j] <= cap_accs) jsel = j;
     uint64_t bt = 0, ba = 0;
     if (jsel >= 0)
       for (uint32_t b = 0; b < blockIdx.x; ++b) {
@@ -256,11 +276,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     s_choice[1] = bt;
     s_choice[2] = ba;
     if (blockIdx.x == 0) {
-      uint64_t tt = 0;
-      if (jsel >= 0)
-        for (uint32_t b = 0; b < nblocks; ++b) tt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
       ctl[kCtlNext] = 0;
-      ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt : 0;
+      ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
       ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
       ctl[kCtlError] = jsel >= 0 ? 0 : 1;
     }
@@ -405,16 +422,14 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
         __hip_atomic_fetch_add(acc + t * kBlock + j1, term1[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    __threadfence();
-    __builtin_amdgcn_wave_barrier();
+    complete_atomics();
     uint32_t old = 0;
-    if (lane == 0)
-      old = __hip_atomic_fetch_add(c.gcnt + idx, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) old = __hip_atomic_fetch_add(c.gcnt + idx, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     old = uniform(old);
     if (old != kFan - 1) return;
-    // the 8th child: the parent is complete; read and clear its accumulator
-    // and counter (they stay zero for the next launch)
-    __threadfence();
+    // the 8th child: every sibling's terms are in; read and clear the
+    // accumulator and its counter (they stay zero for the next launch)
+    complete_atomics();
     if (owner) {
 #pragma unroll
       for (int t = 0; t < K; ++t) {
@@ -603,15 +618,13 @@ __global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
           if (lane == t) v = F[t];
         __hip_atomic_fetch_add(sacc + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __threadfence();
-      __builtin_amdgcn_wave_barrier();
+      complete_atomics();
       uint32_t old = 0;
-      if (lane == 0)
-        old = __hip_atomic_fetch_add(a.sdone + s, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) old = __hip_atomic_fetch_add(a.sdone + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       old = uniform(old);
       if (old == ntask - 1) {
         // last task of the string: read and clear the sums and the counter
-        __threadfence();
+        complete_atomics();
         if (lane < K) {
           uint64_t v = __hip_atomic_exchange(sacc + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __builtin_memcpy(o + 8 * lane, &v, 8);
@@ -663,8 +676,8 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.task_string,
-                     p.task_start, p.acc_start, p.ctl);
+                     p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
+                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.ctl);
   return hipGetLastError();
 }
 

@@ -70,7 +70,12 @@ struct Workspace {
 struct Tuning {
   uint32_t waves_per_cu = 0;
   uint32_t min_j = 0;
+  uint32_t max_j = hth::kPlanCandidates - 1;
 };
+
+// The planner prefers the coarsest task size that still gives this many
+// tasks per resident wave.
+constexpr uint64_t kTasksPerWave = 2;
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
@@ -251,14 +256,16 @@ hth_status hth_reserve(uint64_t max_count, hipStream_t stream) {
   return get_ws(max_count ? max_count : 1, stream, &w);
 }
 
-hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level) {
+hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level,
+                          uint32_t max_task_level) {
   if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_set_tuning: out_width %u", out_width);
-  if (min_task_level >= (uint32_t)hth::kPlanCandidates)
-    return fail(HTH_E_INVALID, "hth_set_tuning: min_task_level %u", min_task_level);
+  if (min_task_level > max_task_level || max_task_level >= (uint32_t)hth::kPlanCandidates)
+    return fail(HTH_E_INVALID, "hth_set_tuning: task levels %u..%u", min_task_level, max_task_level);
   std::lock_guard<std::mutex> lk(g_mu);
   const int wi = width_index(out_width);
   g_tune[wi].waves_per_cu = waves_per_cu;
   g_tune[wi].min_j = min_task_level;
+  g_tune[wi].max_j = max_task_level;
   for (auto it = g_grid.begin(); it != g_grid.end();) {
     if (it->first.second == wi) it = g_grid.erase(it);
     else ++it;
@@ -291,10 +298,10 @@ hth_status hth_hash_batch_timed(const hth_seed* seed, const uint8_t* bytes, cons
   uint32_t grid = 0;
   st = grid_for(out_width, &grid);
   if (st != HTH_OK) return st;
-  uint32_t min_j;
+  Tuning tune;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    min_j = g_tune[width_index(out_width)].min_j;
+    tune = g_tune[width_index(out_width)];
   }
 
   hth::PlanArgs p{};
@@ -304,7 +311,9 @@ hth_status hth_hash_batch_timed(const hth_seed* seed, const uint8_t* bytes, cons
   p.block_sums = w->block_sums;
   p.cap_tasks = w->cap_tasks;
   p.cap_accs = w->cap_accs;
-  p.min_j = min_j;
+  p.min_j = tune.min_j;
+  p.max_j = tune.max_j;
+  p.target_tasks = (uint64_t)grid * kTasksPerWave;
   p.task_string = w->task_string;
   p.task_start = w->task_start;
   p.acc_start = w->acc_start;

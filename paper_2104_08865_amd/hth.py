@@ -58,7 +58,7 @@ def lib():
         L.hth_hash_batch_timed.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp, vp, vp]
         L.hth_reserve.argtypes = [u64, vp]
         L.hth_batch_check.argtypes = [vp]
-        L.hth_set_tuning.argtypes = [u32, u32, u32]
+        L.hth_set_tuning.argtypes = [u32, u32, u32, u32]
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
                      "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning"):
             getattr(L, name).restype = ctypes.c_int32
@@ -126,8 +126,9 @@ def reserve(max_count, stream=None):
     _check(lib().hth_reserve(max_count, _stream(stream)))
 
 
-def set_tuning(out_width, waves_per_cu=0, min_task_level=0):
-    _check(lib().hth_set_tuning(out_width, waves_per_cu, min_task_level))
+def set_tuning(out_width, waves_per_cu=0, min_task_level=0, max_task_level=5):
+    """Grid size and task-size range of the batched kernel for one width."""
+    _check(lib().hth_set_tuning(out_width, waves_per_cu, min_task_level, max_task_level))
 
 
 def batch_check(stream=None):

@@ -52,8 +52,9 @@ def test_host_side_rejections(lib):
     assert rc == hth.HTH_E_INVALID and b"out_width" in lib.hth_last_error()
     rc = lib.hth_hash_batch(None, p, p, p, 1, p, 16, None)
     assert rc == hth.HTH_E_INVALID and b"seed" in lib.hth_last_error()
-    assert lib.hth_set_tuning(20, 0, 0) == hth.HTH_E_INVALID
-    assert lib.hth_set_tuning(16, 0, 9) == hth.HTH_E_INVALID
+    assert lib.hth_set_tuning(20, 0, 0, 5) == hth.HTH_E_INVALID
+    assert lib.hth_set_tuning(16, 0, 0, 9) == hth.HTH_E_INVALID
+    assert lib.hth_set_tuning(16, 0, 3, 2) == hth.HTH_E_INVALID
     h = ctypes.c_void_p()
     assert lib.hth_seed_from_entropy(None, 18369, ctypes.byref(h), None) == hth.HTH_E_INVALID
     assert lib.hth_expand_seed(1, None, None) == hth.HTH_E_INVALID

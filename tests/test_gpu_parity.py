@@ -83,10 +83,11 @@ def test_tree_boundaries(env, width):
     _check(env, data, offs, lens, width, "tree boundaries")
 
 
-@pytest.mark.parametrize("level", [1, 2])
-def test_coarse_tasks_same_result(env, level):
-    """Coarser tasks fold levels 3.. inside one wave instead of across tasks:
-    the values must not change."""
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_forced_task_levels_same_result(env, level):
+    """Every task size gives the oracle's values: level 0 merges every level
+    from 3 up across tasks with device atomics, coarser levels fold the lower
+    ones inside one wave."""
     hth = env["hth"]
     width = 24
     xb = wl.execution_bytes(width)
@@ -94,10 +95,10 @@ def test_coarse_tasks_same_result(env, level):
     offs, total = wl.pack(lens)
     data = wl.random_bytes(13, total)
     try:
-        hth.set_tuning(width, 0, level)
+        hth.set_tuning(width, 0, level, level)
         _check(env, data, offs, lens, width, f"task level {level}")
     finally:
-        hth.set_tuning(width, 0, 0)
+        hth.set_tuning(width)
 
 
 def test_batch_invariance_and_overlap(env):
@@ -128,11 +129,15 @@ def test_raw_entropy_seed(env):
         assert (g == c).all()
 
 
+@pytest.mark.parametrize("level", [None, 0])
 @pytest.mark.parametrize("width", WIDTHS)
-def test_throughput_batch_sampled(env, width):
+def test_throughput_batch_sampled(env, width, level):
     """The 4096 x 1 MiB batch hashed in one launch (the benchmark's
-    configuration); 64 sampled strings checked against the oracle."""
+    configuration, and with the finest tasks, which merge every string across
+    tasks); 64 sampled strings checked against the oracle."""
     torch, hth = env["torch"], env["hth"]
+    if level is not None:
+        hth.set_tuning(width, 0, level, level)
     print(f"[parity] 4096 x 1 MiB width={width}", flush=True)
     n, sz = 4096, 1 << 20
     data = wl.random_bytes_torch(2, n * sz, "cuda")
@@ -148,6 +153,7 @@ def test_throughput_batch_sampled(env, width):
     strs = np.stack([wl.random_bytes(2, sz, start_byte=int(i) * sz) for i in sample])
     ref = env["oracle"].hash_batch(ent2, strs.ravel(), np.arange(sample.size, dtype=np.uint64) * np.uint64(sz),
                                    np.full(sample.size, sz, dtype=np.uint64), width, nthreads=NTHREADS)
+    hth.set_tuning(width)
     assert (out[sample] == ref).all()
     del data
     torch.cuda.empty_cache()
@@ -223,12 +229,13 @@ def test_long_string_8gib_decompositions_agree(env):
     o = torch.zeros(1, dtype=torch.int64, device="cuda")
     n = torch.full((1,), sz, dtype=torch.int64, device="cuda")
     seed4 = hth.expand_seed(4)
-    a = hth.hash_batch(seed4, data, o, n, 32).cpu()
     try:
-        hth.set_tuning(32, 0, 2)
+        hth.set_tuning(32, 0, 0, 0)
+        a = hth.hash_batch(seed4, data, o, n, 32).cpu()
+        hth.set_tuning(32, 0, 2, 2)
         b = hth.hash_batch(seed4, data, o, n, 32).cpu()
     finally:
-        hth.set_tuning(32, 0, 0)
+        hth.set_tuning(32)
     assert (a == b).all()
     del data
     torch.cuda.empty_cache()
