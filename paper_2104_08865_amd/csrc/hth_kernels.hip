@@ -63,6 +63,13 @@ __device__ __forceinline__ uint64_t mulc(int c, uint64_t h) {
   }
 }
 
+// Keys that every lane of a wave reads at the same address go through the
+// scalar cache: the constant address space lets the compiler use scalar loads
+// (counted apart from the vector loads of the data, so they never delay the
+// data's waits) and keep the keys out of vector registers.
+typedef const __attribute__((address_space(4))) uint64_t* key_ptr;
+__device__ __forceinline__ key_ptr uniform_keys(const uint64_t* p) { return (key_ptr)p; }
+
 __device__ __forceinline__ uint4 load16(const uint8_t* p) {
   uint4 v;
   __builtin_memcpy(&v, p, 16);
@@ -116,7 +123,7 @@ __device__ __forceinline__ uint64_t nodes_at(uint64_t N, int l) { return l >= 22
 // ---------------------------------------------------------------------------
 
 template <int WIDTH>
-__device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, const uint64_t* __restrict__ S_ehc,
+__device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_ehc,
                                      uint64_t z0[], uint64_t z1[]) {
   using Fm = Family<WIDTH>;
   constexpr int D = Fm::D, K = Fm::K, R = K - 1;
@@ -498,13 +505,13 @@ __global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
       for (int e = 0; e < 8; ++e) {
         if (e < cnt) {
           uint64_t z0[K], z1[K];
-          ehc2<WIDTH>(col + e * XB, ent + Ly::ehc, z0, z1);
+          ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
           if (cnt == 8) {
             // level 0 of every tree: child e of this lane's level-1 node
             if (e < kFan - 1) {
 #pragma unroll
               for (int t = 0; t < K; ++t) {
-                const uint64_t key = ent[Ly::tree + (t * kLevels) * (kFan - 1) + e];
+                const uint64_t key = uniform_keys(ent)[Ly::tree + (t * kLevels) * (kFan - 1) + e];
                 a0[t] = nh_acc(a0[t], z0[t], key);
                 a1[t] = nh_acc(a1[t], z1[t], key);
               }
