@@ -134,7 +134,7 @@ hth_status hth_batch_check(hipStream_t stream);
 
 /* Tuning of the batched kernel for one output width; applies to later calls.
    waves_per_cu: resident single-wave workgroups per compute unit of the
-   persistent grid (0 = the occupancy limit, the default).  A task covers
+   persistent grid (0 = the default, 8, or the occupancy limit if lower).  A task covers
    128 * 8^j full EHC executions of one string; the planner picks j in
    [min_task_level, max_task_level] (defaults 0 and 5): the coarsest level that
    still gives two tasks per resident wave, finer only if the workspace

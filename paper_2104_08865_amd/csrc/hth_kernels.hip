@@ -201,28 +201,48 @@ constexpr int kPlanThreads = 256;
 constexpr int kPlanPer = 4;
 constexpr int kPlanBlock = kPlanThreads * kPlanPer;
 
-template <typename T>
-__device__ T block_exclusive_scan(T v, T* lds, T& total) {
-  // Hillis-Steele over 256 threads; lds holds 256 entries.
-  const int tid = threadIdx.x;
-  lds[tid] = v;
+constexpr int kPlanWaves = kPlanThreads / 64;
+
+// Sum of v over the block, returned to every thread.
+__device__ uint64_t block_sum(uint64_t v, uint64_t* lds) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
   __syncthreads();
-  for (int off = 1; off < kPlanThreads; off <<= 1) {
-    T add = tid >= off ? lds[tid - off] : 0;
-    __syncthreads();
-    lds[tid] += add;
-    __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kPlanWaves; ++i) t += lds[i];
+  return t;
+}
+
+// Exclusive prefix sum of v over the block (thread order); `total` receives
+// the block's sum.
+__device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = shfl64(x, lane >= d ? lane - d : lane);
+    if (lane >= d) x += y;
   }
-  T incl = lds[tid];
-  total = lds[kPlanThreads - 1];
   __syncthreads();
-  return incl - v;
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  uint64_t before = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < kPlanWaves; ++i) {
+    if (i < w) before += lds[i];
+    total += lds[i];
+  }
+  return before + x - v;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
                                                                   uint64_t count, uint32_t exec_bytes,
                                                                   uint64_t* __restrict__ block_sums) {
-  __shared__ uint64_t lds[kPlanThreads];
+  __shared__ uint64_t lds[kPlanWaves];
   const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t N[kPlanPer];
   for (int i = 0; i < kPlanPer; ++i) N[i] = base + i < count ? lengths[base + i] / exec_bytes : 0;
@@ -235,12 +255,11 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
       t += ti;
       a += ai;
     }
-    uint64_t tot_t, tot_a;
-    block_exclusive_scan<uint64_t>(t, lds, tot_t);
-    block_exclusive_scan<uint64_t>(a, lds, tot_a);
+    t = block_sum(t, lds);
+    a = block_sum(a, lds);
     if (threadIdx.x == 0) {
-      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j] = tot_t;
-      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j + 1] = tot_a;
+      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j] = t;
+      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j + 1] = a;
     }
   }
 }
@@ -249,62 +268,59 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
-    uint32_t* __restrict__ task_start,
-    uint32_t* __restrict__ acc_start, uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t lds[kPlanThreads];
+    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ ctl) {
+  __shared__ uint64_t lds[kPlanWaves];
   __shared__ uint32_t incl[kPlanBlock];
-  __shared__ uint64_t s_choice[3];  // j, task base, acc base
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    // Task size: the coarsest level in [min_j, max_j] that still yields
-    // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
-    // grid busy), else min_j; then coarser until the plan fits the workspace.
-    uint64_t tt[kPlanCandidates], ta[kPlanCandidates];
-    for (int j = 0; j < kPlanCandidates; ++j) {
-      tt[j] = ta[j] = 0;
-      for (uint32_t b = 0; b < nblocks; ++b) {
-        tt[j] += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
-        ta[j] += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
-      }
+  // Totals of every candidate over all blocks (threads stride over blocks).
+  uint64_t tt[kPlanCandidates], ta[kPlanCandidates];
+  for (int j = 0; j < kPlanCandidates; ++j) {
+    uint64_t t = 0, a = 0;
+    for (uint32_t b = tid; b < nblocks; b += kPlanThreads) {
+      t += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
+      a += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
     }
-    int want = (int)min_j;
-    for (int j = (int)min_j; j <= (int)max_j && j < kPlanCandidates; ++j)
-      if (tt[j] >= target_tasks) want = j;
-    int jsel = -1;
-    for (int j = want; j < kPlanCandidates && jsel < 0; ++j)
-      if (tt[j] <= cap_tasks && ta[j] <= cap_accs) jsel = j;
-    uint64_t bt = 0, ba = 0;
-    if (jsel >= 0)
-      for (uint32_t b = 0; b < blockIdx.x; ++b) {
-        bt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
-        ba += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel + 1];
-      }
-    s_choice[0] = (uint64_t)(int64_t)jsel;
-    s_choice[1] = bt;
-    s_choice[2] = ba;
-    if (blockIdx.x == 0) {
-      ctl[kCtlNext] = 0;
-      ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
-      ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
-      ctl[kCtlError] = jsel >= 0 ? 0 : 1;
-    }
+    tt[j] = block_sum(t, lds);
+    ta[j] = block_sum(a, lds);
   }
-  __syncthreads();
-  const int64_t jsel = (int64_t)s_choice[0];
-  if (jsel < 0) return;
+  // Task size: the coarsest level in [min_j, max_j] that still yields
+  // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
+  // grid busy), else min_j; then coarser until the plan fits the workspace.
+  int want = (int)min_j;
+  for (int j = (int)min_j; j <= (int)max_j && j < kPlanCandidates; ++j)
+    if (tt[j] >= target_tasks) want = j;
+  int jsel = -1;
+  for (int j = want; j < kPlanCandidates && jsel < 0; ++j)
+    if (tt[j] <= cap_tasks && ta[j] <= cap_accs) jsel = j;
+  if (blockIdx.x == 0 && tid == 0) {
+    ctl[kCtlNext] = 0;
+    ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
+    ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
+    ctl[kCtlError] = jsel >= 0 ? 0 : 1;
+  }
+  if (jsel < 0) return;  // uniform over the grid
+  // Tasks and accumulators of the blocks before this one.
+  uint64_t pt = 0, pa = 0;
+  for (uint32_t b = tid; b < blockIdx.x; b += kPlanThreads) {
+    pt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
+    pa += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel + 1];
+  }
+  const uint64_t task_base = block_sum(pt, lds);
+  const uint64_t acc_base = block_sum(pa, lds);
+
   const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + tid * kPlanPer;
   uint64_t tk[kPlanPer], ac[kPlanPer];
   uint64_t st = 0, sa = 0;
   for (int i = 0; i < kPlanPer; ++i) {
     tk[i] = ac[i] = 0;
-    if (base + i < count) plan_counts(lengths[base + i] / exec_bytes, (int)jsel, tk[i], ac[i]);
+    if (base + i < count) plan_counts(lengths[base + i] / exec_bytes, jsel, tk[i], ac[i]);
     st += tk[i];
     sa += ac[i];
   }
   uint64_t blk_t, blk_a;
-  uint64_t et = block_exclusive_scan<uint64_t>(st, lds, blk_t);
-  uint64_t ea = block_exclusive_scan<uint64_t>(sa, lds, blk_a);
-  uint64_t run_t = s_choice[1] + et, run_a = s_choice[2] + ea;
+  const uint64_t et = block_exclusive(st, lds, blk_t);
+  const uint64_t ea = block_exclusive(sa, lds, blk_a);
+  uint64_t run_t = task_base + et, run_a = acc_base + ea;
   uint64_t loc = et;
   for (int i = 0; i < kPlanPer; ++i) {
     if (base + i < count) {
@@ -327,7 +343,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
       if ((uint64_t)incl[mid] > e) hi = mid;
       else lo = mid + 1;
     }
-    task_string[s_choice[1] + e] = (uint32_t)(first + lo);
+    task_string[task_base + e] = (uint32_t)(first + lo);
   }
 }
 

@@ -77,6 +77,11 @@ struct Tuning {
 // tasks per resident wave.
 constexpr uint64_t kTasksPerWave = 2;
 
+// Default resident waves per compute unit of the persistent grid (2 per
+// SIMD): at this depth the hashing kernel already keeps enough loads in
+// flight to reach the HBM read ceiling; more waves only add contention.
+constexpr uint32_t kDefaultWavesPerCU = 8;
+
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 Tuning g_tune[4];
@@ -177,7 +182,8 @@ hth_status grid_for(uint32_t width, uint32_t* grid) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::main_kernel_fn(width), 64, 0);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   uint32_t wpc = per_cu > 0 ? (uint32_t)per_cu : 1;
-  if (g_tune[wi].waves_per_cu && g_tune[wi].waves_per_cu < wpc) wpc = g_tune[wi].waves_per_cu;
+  const uint32_t want = g_tune[wi].waves_per_cu ? g_tune[wi].waves_per_cu : kDefaultWavesPerCU;
+  if (want < wpc) wpc = want;
   *grid = (uint32_t)cus * wpc;
   g_grid[{dev, wi}] = *grid;
   return HTH_OK;
