@@ -20,6 +20,11 @@ Extra objects on the JSON line:
                 bit-for-bit against the GPU output.
 
   python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py --workload uneven   # 200,521 strings of 16 B - 256 KiB, width 24:
+                                      # one persistent launch vs a captured graph vs
+                                      # one launch per string (autotuned launch choice)
+  python bench.py --workload long     # one 8 GiB string, width 32
+Each workload prints one JSON line of the same shape.
 """
 import argparse
 import hashlib
@@ -89,7 +94,7 @@ def cpu_baseline(gpu_out, n_strings, string_bytes, sample_per_width):
     }
 
 
-def main():
+def run_main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -98,6 +103,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384, help="oracle strings per width")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve"), default="throughput")
+    ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per offered load (serve)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -106,6 +114,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "uneven":
+        line = run_uneven(args)
+    elif args.workload == "long":
+        line = run_long(args)
+    elif args.workload == "serve":
+        line = run_serve(args)
+    else:
+        line = run_throughput(args)
+    print(json.dumps(line), flush=True)
+
+
+def run_throughput(args):
     import torch
     from paper_2104_08865_amd import hth
     from paper_2104_08865_amd import workloads as wl
@@ -207,8 +227,258 @@ def main():
         "per_width": per_width,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    if not args.no_serve:
+        del data, outs
+        torch.cuda.empty_cache()
+        line["latency"] = serve_legs(min(args.serve_requests, 50_000))
+    return line
+
+
+SERVE_LOADS = (0.25, 0.5, 0.8)
+
+
+def serve_legs(n_req, verify=False):
+    """The serving workload: lognormal request lengths (median 4 KiB,
+    sigma 2, capped at 16 MiB), widths 16/40 at 50/50, bytes from splitmix64
+    seed 5, replayed from host memory into one server.  First at no pacing
+    (every request due at once) to measure the server's capacity, then with
+    Poisson arrivals at 0.25, 0.5 and 0.8 of that capacity."""
+    import torch
+    from paper_2104_08865_amd import hth
+    from paper_2104_08865_amd import workloads as wl
+
+    lens = wl.lognormal_lengths(seed=5, n=n_req)
+    widths = wl.coin_widths(5, n_req)
+    unit_gaps = wl.poisson_gaps(5, n_req, 1.0)
+    offs, total = wl.pack(lens)
+    log(f"[bench] serving: {n_req} requests, {total} bytes, mean {total / n_req:.0f} B")
+    data = wl.random_bytes(5, total)
+    seed = hth.expand_seed(5)
+    torch.cuda.synchronize()
+    res = {"workload": "serving: lognormal lengths (median 4 KiB, sigma 2, cap 16 MiB), widths 16/40 50/50, "
+                       "bytes splitmix64 seed 5, submitted from host memory; Poisson arrivals",
+           "requests_per_load": n_req, "mean_request_bytes": total / n_req, "loads": []}
+    with hth.Server(seed, max_device_bytes=2 << 30, host_stage_bytes=2 << 30) as srv:
+        # capacity: every request due at once
+        tickets = srv.replay(data, offs, lens, widths, np.zeros(n_req, dtype=np.uint64))
+        got = srv.wait_many(tickets)
+        st = srv.stats()
+        cap_rps = st["completed"] / st["elapsed_s"]
+        res["capacity"] = {"requests_per_s": cap_rps, "GBps": st["gbps"], "p50_us": st["latency_p50_us"],
+                           "p99_us": st["latency_p99_us"], "mean_batch_requests": st["mean_batch_requests"]}
+        log(f"[bench] serving capacity {cap_rps:.0f} req/s, {st['gbps']:.1f} GB/s")
+        for load in SERVE_LOADS:
+            rate = load * cap_rps
+            arrive = (np.cumsum(unit_gaps) / rate * 1e9).astype(np.uint64)
+            srv.reset_stats()
+            tickets = srv.replay(data, offs, lens, widths, arrive)
+            out = srv.wait_many(tickets)
+            st = srv.stats()
+            same = bool((out == got).all())
+            res["loads"].append({"offered_fraction_of_capacity": load, "offered_requests_per_s": rate,
+                                 "achieved_requests_per_s": st["completed"] / st["elapsed_s"],
+                                 "GBps": st["gbps"], "p50_us": st["latency_p50_us"], "p99_us": st["latency_p99_us"],
+                                 "max_us": st["latency_max_us"], "mean_batch_requests": st["mean_batch_requests"],
+                                 "deferred": st["deferred"], "busy": st["busy"], "same_as_capacity_run": same})
+            log(f"[bench] load {load}: p50 {st['latency_p50_us']:.0f} us, p99 {st['latency_p99_us']:.0f} us, "
+                f"{st['gbps']:.1f} GB/s, identical={same}")
+    if verify:
+        # every served result equals the batched path's
+        dev = torch.device("cuda:0")
+        d = torch.from_numpy(data).to(dev)
+        o = torch.from_numpy(offs.view(np.int64)).to(dev)
+        n = torch.from_numpy(lens.view(np.int64)).to(dev)
+        ok = True
+        for w in (16, 40):
+            sel = torch.from_numpy(np.nonzero(widths == w)[0]).to(dev)
+            ref = hth.hash_batch(seed, d, o[sel], n[sel], w).cpu().numpy()
+            ok &= bool((got[sel.cpu().numpy(), :w] == ref).all())
+        res["served_equals_batched"] = ok
+        del d
+    return res
+
+
+def run_serve(args):
+    """Serving workload line: value = served GB/s at capacity."""
+    import torch
+    torch.cuda.set_device(torch.device("cuda:0"))
+    res = serve_legs(args.serve_requests, verify=True)
+    cap = res["capacity"]
+    return {
+        "metric": "hashed GB/s vs HBM peak (bit-exact to oracle); p50/p99 latency at fixed rate",
+        "value": cap["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": args.serve_requests / cap["requests_per_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": res["workload"], "requests_per_load": res["requests_per_load"]},
+        "latency": res, "cpu_baseline": None,
+    }
+
+
+def _roofline(kernel, algo_bytes, avg_ms, traffic=None):
+    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": algo_bytes, "avg_launch_ms": avg_ms}
+
+
+def _timed_launches(hth, torch, launch, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        launch()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_uneven(args):
+    """200,000 log-uniform lengths in [16 B, 256 KiB) plus every length 0..520
+    (bytes from splitmix64 seed 3, packed back to back, so most strings start
+    unaligned), width 24."""
+    import ctypes
+
+    import torch
+    import oracle
+    from paper_2104_08865_amd import autotune, hth
+    from paper_2104_08865_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    width = 24
+    lens = wl.uneven_lengths(3)
+    offs, total = wl.pack(lens)
+    count = lens.size
+    log(f"[bench] uneven batch: {count} strings, {total} bytes")
+    data = wl.random_bytes_torch(3, total, dev)
+    o = torch.from_numpy(offs.view(np.int64)).to(dev)
+    n = torch.from_numpy(lens.view(np.int64)).to(dev)
+    seed = hth.expand_seed(3)
+    hth.reserve(count)
+    choice, times = autotune.tune(seed, data, o, n, width, total_bytes=total, use_cache=False)
+    log(f"[bench] autotuned launch choice (waves/CU, min level, max level) = {choice}")
+    out = torch.empty((count, width), dtype=torch.uint8, device=dev)
+
+    # one persistent launch per step
+    for _ in range(args.warmup):
+        hth.hash_batch(seed, data, o, n, width, out=out)
+    timers = [hth.Timer() for _ in range(args.steps)]
+    it = iter(timers)
+    wall = _timed_launches(hth, torch, lambda: hth.hash_batch(seed, data, o, n, width, out=out, timer=next(it)),
+                           args.steps)
+    hth.batch_check()
+    kernel_ms = float(np.mean([t.elapsed_ms() for t in timers]))
+    persistent = out.cpu().numpy()
+
+    # the same launch captured in a graph
+    g = hth.BatchGraph(seed, data, o, n, width)
+    for _ in range(args.warmup):
+        g.launch()
+    gwall = _timed_launches(hth, torch, g.launch, args.steps)
+    g.check()
+    graph_out = g.out.cpu().numpy()
+
+    # one launch of the same library call per string
+    L = hth.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    per = torch.empty((count, width), dtype=torch.uint8, device=dev)
+    sp, dp, op, np_, pp = seed.handle, ctypes.c_void_p(data.data_ptr()), o.data_ptr(), n.data_ptr(), per.data_ptr()
+    log("[bench] per-string launches ...")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        rc = L.hth_hash_batch(sp, dp, ctypes.c_void_p(op + 8 * i), ctypes.c_void_p(np_ + 8 * i), 1,
+                              ctypes.c_void_p(pp + width * i), width, stream)
+        if rc:
+            raise RuntimeError(L.hth_last_error())
+    torch.cuda.synchronize()
+    swall = time.perf_counter() - t0
+    per_out = per.cpu().numpy()
+    agree = bool((persistent == graph_out).all() and (persistent == per_out).all())
+    log(f"[bench] persistent {total / wall * args.steps / 1e9:.0f} GB/s, graph {total / gwall * args.steps / 1e9:.0f} "
+        f"GB/s, per-string {total / swall / 1e9:.1f} GB/s, identical={agree}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        idx = np.arange(0, count, 20)
+        sub_lens = lens[idx]
+        sub_offs, sub_total = wl.pack(sub_lens)
+        sub = np.concatenate([wl.random_bytes(3, int(lens[i]), start_byte=int(offs[i])) for i in idx])
+        ent = oracle.expand_seed(3)
+        t0 = time.perf_counter()
+        ref = oracle.hash_batch(ent, sub, sub_offs, sub_lens, width, nthreads=1)
+        dt = time.perf_counter() - t0
+        cpu = {"value": sub_total / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"every 20th string of the batch ({idx.size} strings, {sub_total} bytes), single thread",
+               "seconds": dt, "bit_exact_vs_gpu": bool((ref == persistent[idx]).all())}
+
+    algo = total + 16 * count + width * count
+    return {
+        "metric": "hashed GB/s vs HBM peak (bit-exact to oracle); p50/p99 latency at fixed rate",
+        "value": total * args.steps / wall / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "uneven batch: 200,000 log-uniform lengths in [16 B, 256 KiB) plus every length "
+                               "0..520, packed back to back (splitmix64 seed 3), width 24, one persistent launch",
+                   "strings": int(count), "bytes": int(total), "width": width, "seed": 3,
+                   "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms),
+        "graph_replay_GBps": total * args.steps / gwall / 1e9,
+        "per_string_launches_GBps": total / swall / 1e9,
+        "persistent_over_per_string": (total * args.steps / wall) / (total / swall),
+        "all_three_identical": agree,
+        "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
+        "cpu_baseline": cpu,
+    }
+
+
+def run_long(args):
+    """One 8 GiB string of uniformly random bytes (splitmix64 seed 4), width 32."""
+    import torch
+    import oracle
+    from paper_2104_08865_amd import autotune, hth
+    from paper_2104_08865_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    width, sz = 32, 8 << 30
+    log("[bench] one 8 GiB string")
+    data = wl.random_bytes_torch(4, sz, dev)
+    o = torch.zeros(1, dtype=torch.int64, device=dev)
+    n = torch.full((1,), sz, dtype=torch.int64, device=dev)
+    seed = hth.expand_seed(4)
+    choice, times = autotune.tune(seed, data, o, n, width, total_bytes=sz, use_cache=False)
+    log(f"[bench] autotuned launch choice = {choice}")
+    out = torch.empty((1, width), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        hth.hash_batch(seed, data, o, n, width, out=out)
+    timers = [hth.Timer() for _ in range(args.steps)]
+    it = iter(timers)
+    wall = _timed_launches(hth, torch, lambda: hth.hash_batch(seed, data, o, n, width, out=out, timer=next(it)),
+                           args.steps)
+    hth.batch_check()
+    kernel_ms = float(np.mean([t.elapsed_ms() for t in timers]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        pre = 1 << 29
+        sample = wl.random_bytes(4, pre)
+        t0 = time.perf_counter()
+        oracle.hash_bytes(oracle.expand_seed(4), sample, width)
+        dt = time.perf_counter() - t0
+        cpu = {"value": pre / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "the first 512 MiB of the string hashed as one string, single thread", "seconds": dt}
+    algo = sz + 16 + width
+    return {
+        "metric": "hashed GB/s vs HBM peak (bit-exact to oracle); p50/p99 latency at fixed rate",
+        "value": sz * args.steps / wall / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "one 8 GiB string of uniform random bytes (splitmix64 seed 4), width 32",
+                   "bytes": sz, "width": width, "seed": 4,
+                   "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms),
+        "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
+        "cpu_baseline": cpu,
+    }
 
 
 if __name__ == "__main__":
-    main()
+    run_main()

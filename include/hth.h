@@ -124,6 +124,37 @@ hth_status hth_hash_batch_timed(const hth_seed *seed, const uint8_t *bytes, cons
                                 uint32_t out_width, hipStream_t stream, hipEvent_t main_start,
                                 hipEvent_t main_stop);
 
+/* ------------------------------------------------------------------------ */
+/* Captured batches (HIP graphs).                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hth_batch_graph hth_batch_graph;
+
+/* Capture one hth_hash_batch call (planner and hashing kernel) into a HIP
+   graph for repeated launches: the pointers and count are fixed at creation,
+   the contents of bytes/offsets/lengths may change between launches (every
+   launch plans from the device arrays again).  The graph owns a private
+   workspace, so launches of one graph must not overlap (launch it on one
+   stream, or order the streams); different graphs are independent.  The
+   captured work contains kernels only (no memset nodes).  Synchronous
+   with respect to the host while it captures.
+   Errors: HTH_E_INVALID (as hth_hash_batch, or count == 0), HTH_E_OOM,
+   HTH_E_HIP. */
+hth_status hth_batch_graph_create(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
+                                  const uint64_t *lengths, uint64_t count, uint8_t *out,
+                                  uint32_t out_width, hth_batch_graph **graph);
+
+/* Enqueue one launch of the captured batch on `stream`. */
+hth_status hth_batch_graph_launch(hth_batch_graph *graph, hipStream_t stream);
+
+/* Synchronise `stream` and report the planner status of the graph's last
+   launch (HTH_OK or HTH_E_TOO_LARGE, as hth_batch_check). */
+hth_status hth_batch_graph_check(hth_batch_graph *graph, hipStream_t stream);
+
+/* Release a graph and its workspace (after its launches have completed).
+   Null is accepted. */
+hth_status hth_batch_graph_free(hth_batch_graph *graph);
+
 /* Pre-size the workspace of `stream` for batches of up to max_count strings.
    Synchronous with respect to the host.  Errors: HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_reserve(uint64_t max_count, hipStream_t stream);
@@ -142,6 +173,99 @@ hth_status hth_batch_check(hipStream_t stream);
    Errors: HTH_E_INVALID (bad width, min > max, max > 5). */
 hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t min_task_level,
                           uint32_t max_task_level);
+
+/* ------------------------------------------------------------------------ */
+/* Serving loop.  Hash requests arrive one at a time as host bytes; a       */
+/* server admits them by device memory, gathers whatever has arrived into   */
+/* batches (continuous batching: a batch leaves as soon as a stream slot is */
+/* free) and hashes every batch with the planner and kernel of             */
+/* hth_hash_batch, so a request's value does not depend on what it was     */
+/* batched with.  A worker thread per server does the scheduling.           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hth_server hth_server;
+
+typedef struct hth_serve_config {
+  uint64_t max_device_bytes;   /* device memory for request bytes in flight: the
+                                  admission budget (0: 1 GiB) */
+  uint64_t host_stage_bytes;   /* pinned host staging for submitted bytes (0: 1 GiB) */
+  uint64_t max_request_bytes;  /* larger requests are refused (0: 16 MiB); must fit
+                                  both of the above */
+  uint64_t max_batch_bytes;    /* a batch stops growing at this many bytes
+                                  (0: 64 MiB, at most 2^36) */
+  uint32_t max_batch_requests; /* and at this many requests (0: 16384, at most 2^22) */
+  uint32_t slots;              /* batches in flight, one stream each (0: 3, at most 8) */
+  uint32_t max_outstanding;    /* submitted requests whose results are not yet
+                                  collected (0: 2^20, at most 2^24; rounded up
+                                  to a power of two) */
+  uint32_t reserved;           /* set to 0 */
+} hth_serve_config;
+
+typedef struct hth_serve_report {
+  uint64_t submitted;   /* requests accepted by submit */
+  uint64_t completed;   /* results visible to poll/wait */
+  uint64_t deferred;    /* requests that had to wait for device memory */
+  uint64_t busy;        /* submits refused with HTH_E_BUSY */
+  uint64_t batches;     /* batches hashed */
+  uint64_t bytes;       /* request bytes hashed */
+  double elapsed_s;     /* first submit to last completion */
+  double gbps;          /* bytes / elapsed_s, in 10^9 bytes per second */
+  double latency_p50_us, latency_p99_us, latency_max_us, latency_mean_us;
+                        /* submit -> result visible, over completed requests */
+  double mean_batch_requests;
+} hth_serve_report;
+
+/* Create a server on the current device for `seed` (which must outlive it).
+   Allocates the device budget, the pinned staging, per-slot streams and
+   workspaces, and starts the worker thread.  Unset (zero) fields take the
+   defaults above.  Errors: HTH_E_INVALID (null pointer, limits out of range
+   or inconsistent, seed on another device), HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_serve_create(const hth_serve_config *config, const hth_seed *seed, hth_server **out);
+
+/* Submit one request: `len` bytes at host pointer host_bytes (copied before
+   the call returns; the caller may reuse the memory), hashed to out_width
+   (16, 24, 32 or 40) bytes.  *ticket receives the request's ticket.
+   The request waits in the queue while the device budget is full (counted
+   as deferred).  Errors: HTH_E_TOO_LARGE (len > max_request_bytes),
+   HTH_E_BUSY (staging full or max_outstanding results uncollected: retry
+   later), HTH_E_INVALID, HTH_E_HIP (the server stopped after an error). */
+hth_status hth_serve_submit(hth_server *server, const void *host_bytes, uint64_t len, uint32_t out_width,
+                            uint64_t *ticket);
+
+/* Collect a result without blocking: HTH_OK copies out_width bytes to
+   out_host and retires the ticket; HTH_E_BUSY means not ready yet;
+   HTH_E_INVALID for an unknown or already collected ticket. */
+hth_status hth_serve_poll(hth_server *server, uint64_t ticket, uint8_t *out_host);
+
+/* As hth_serve_poll, but blocks until the result is ready. */
+hth_status hth_serve_wait(hth_server *server, uint64_t ticket, uint8_t *out_host);
+
+/* hth_serve_wait for n tickets; result i goes to out_host + i * out_stride
+   (out_stride >= 40). */
+hth_status hth_serve_wait_many(hth_server *server, const uint64_t *tickets, uint64_t n, uint8_t *out_host,
+                               uint32_t out_stride);
+
+/* Load replay: submits request i (bytes base + offsets[i], lengths[i],
+   width widths[i]) at arrival_ns[i] nanoseconds after the call starts
+   (non-decreasing), retrying while the server answers HTH_E_BUSY; tickets
+   go to tickets[i].  Returns after the last submit, not after completion. */
+hth_status hth_serve_replay(hth_server *server, const uint8_t *base, const uint64_t *offsets,
+                            const uint64_t *lengths, const uint32_t *widths, const uint64_t *arrival_ns,
+                            uint64_t n, uint64_t *tickets);
+
+/* Hold (paused != 0) or release (0) batching: while held, submitted
+   requests queue up (within the staging and outstanding limits) and no new
+   batch starts; batches already in flight complete.  For bursts that should
+   leave together, and for draining a server without new device work. */
+hth_status hth_serve_pause(hth_server *server, int32_t paused);
+
+/* Counters and latency percentiles since creation or the last reset. */
+hth_status hth_serve_stats(hth_server *server, hth_serve_report *out);
+hth_status hth_serve_reset_stats(hth_server *server);
+
+/* Stop the worker (after the batches in flight complete) and free the
+   server; uncollected results are dropped.  Null is accepted. */
+hth_status hth_serve_destroy(hth_server *server);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,59 @@
+// Host-side internals shared by the C ABI files of libhth (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/hth.h"
+
+struct hth_seed {
+  int device = 0;
+  uint64_t* d_words = nullptr;
+  std::vector<uint64_t> host;
+};
+
+namespace hth {
+namespace host {
+
+// Workspace of one (device, stream): planning arrays and the cross-task
+// accumulators.  sacc, sdone, gacc and gcnt hold zeros between launches (the
+// kernel that consumes an accumulator resets it), so a workspace is cleared
+// only once, when it is allocated.
+struct Workspace {
+  uint64_t cap_count = 0, cap_tasks = 0, cap_accs = 0, cap_blocks = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  uint32_t* ctl = nullptr;
+  uint64_t* block_sums = nullptr;
+  uint32_t* task_string = nullptr;
+  uint32_t* task_start = nullptr;
+  uint32_t* acc_start = nullptr;
+  uint32_t* bucket_lead = nullptr;
+  uint64_t* sacc = nullptr;
+  uint32_t* sdone = nullptr;
+  uint64_t* gacc = nullptr;
+  uint32_t* gcnt = nullptr;
+};
+
+// Error reporting: sets the thread's hth_last_error message, returns code.
+hth_status fail(hth_status code, const char* fmt, ...);
+hth_status hip_fail(hipError_t e, const char* what);
+bool width_ok(uint32_t w);
+
+// (Re)allocates w with room for `count` strings, zeroed; the old workspace
+// is freed after `stream` drains.
+hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream);
+
+// Validates the arguments of one batch (as hth_hash_batch).
+hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                            const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width);
+
+// Enqueues the planner and the hashing kernel of one batch on `stream`
+// using workspace `w` (events optional, recorded around the hashing kernel).
+hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                         const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop);
+
+}  // namespace host
+}  // namespace hth

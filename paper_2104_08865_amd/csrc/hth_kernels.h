@@ -9,20 +9,40 @@ namespace hth {
 constexpr int kMaxK = 5;            // largest number of output words (40 bytes)
 constexpr int kPlanCandidates = 6;  // task sizes 128 * 8^j, j = 0..5
 
+// Work distribution: the planner cuts the task list into buckets of about
+// equal work (string bytes plus a per-task overhead), at most kMaxBuckets of
+// at least kMinBucketBytes each.  A bucket is the run of tasks from a leader
+// (the first task starting at or after a bucket boundary) up to the next
+// leader, so a task longer than a bucket never leaves empty buckets behind.
+// Waves take whole buckets from one device counter: one atomic per bucket,
+// not per task, so runs of short strings cost one fetch between them.
+constexpr uint32_t kMaxBuckets = 1u << 16;
+constexpr uint64_t kMinBucketBytes = 128u << 10;
+constexpr uint64_t kTaskOverheadBytes = 4096;
+constexpr int kPlanSums = 3;  // per candidate task size: tasks, accumulators, work
+
 // Control words of one launch (device memory, written by the planner).
-enum { kCtlNext = 0, kCtlTotal = 1, kCtlLevel = 2, kCtlError = 3, kCtlWords = 4 };
+enum {
+  kCtlNext = 0,  // next bucket to hand out
+  kCtlTotal,     // number of tasks
+  kCtlLevel,
+  kCtlError,
+  kCtlBuckets,   // number of buckets (leaders)
+  kCtlWords = 16
+};
 
 struct PlanArgs {
   const uint64_t* lengths;
   uint64_t count;
   uint32_t exec_bytes;
-  uint64_t* block_sums;  // [nblocks][2 * kPlanCandidates]
+  uint64_t* block_sums;  // [nblocks][kPlanCandidates][kPlanSums]
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
-  uint32_t* task_string;  // [cap_tasks]
+  uint32_t* task_string;  // [cap_tasks]: string of each task, bit 31 set on bucket leaders
   uint32_t* task_start;   // [count]
   uint32_t* acc_start;    // [count]
+  uint32_t* bucket_lead;  // [kMaxBuckets]: leader task of each bucket, any order
   uint32_t* ctl;          // [kCtlWords]
 };
 
@@ -39,6 +59,7 @@ struct MainArgs {
   uint32_t* sdone; // [count], zero between launches
   uint64_t* gacc;  // [cap_accs][kMaxK * 8], zero between launches
   uint32_t* gcnt;  // [cap_accs], zero between launches
+  const uint32_t* bucket_lead;
   uint32_t* ctl;
 };
 

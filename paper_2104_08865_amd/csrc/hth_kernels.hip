@@ -241,25 +241,32 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
                                                                   uint64_t count, uint32_t exec_bytes,
-                                                                  uint64_t* __restrict__ block_sums) {
+                                                                  uint64_t* __restrict__ block_sums,
+                                                                  uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
+  // the fill kernel appends bucket leaders to this counter
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + threadIdx.x * kPlanPer;
-  uint64_t N[kPlanPer];
-  for (int i = 0; i < kPlanPer; ++i) N[i] = base + i < count ? lengths[base + i] / exec_bytes : 0;
+  uint64_t L[kPlanPer];
+  for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
   for (int j = 0; j < kPlanCandidates; ++j) {
-    uint64_t t = 0, a = 0;
+    uint64_t t = 0, a = 0, w = 0;
     for (int i = 0; i < kPlanPer; ++i) {
       if (base + i >= count) continue;
       uint64_t ti, ai;
-      plan_counts(N[i], j, ti, ai);
+      plan_counts(L[i] / exec_bytes, j, ti, ai);
       t += ti;
       a += ai;
+      w += L[i] + kTaskOverheadBytes * ti;
     }
     t = block_sum(t, lds);
     a = block_sum(a, lds);
+    w = block_sum(w, lds);
     if (threadIdx.x == 0) {
-      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j] = t;
-      block_sums[(uint64_t)blockIdx.x * 2 * kPlanCandidates + 2 * j + 1] = a;
+      uint64_t* bs = block_sums + ((uint64_t)blockIdx.x * kPlanCandidates + j) * kPlanSums;
+      bs[0] = t;
+      bs[1] = a;
+      bs[2] = w;
     }
   }
 }
@@ -268,20 +275,25 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
-    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
+    uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
   __shared__ uint32_t incl[kPlanBlock];
+  __shared__ uint64_t wstart[kPlanBlock];
   const int tid = threadIdx.x;
   // Totals of every candidate over all blocks (threads stride over blocks).
-  uint64_t tt[kPlanCandidates], ta[kPlanCandidates];
+  uint64_t tt[kPlanCandidates], ta[kPlanCandidates], tw[kPlanCandidates];
   for (int j = 0; j < kPlanCandidates; ++j) {
-    uint64_t t = 0, a = 0;
+    uint64_t t = 0, a = 0, w = 0;
     for (uint32_t b = tid; b < nblocks; b += kPlanThreads) {
-      t += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j];
-      a += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * j + 1];
+      const uint64_t* bs = block_sums + ((uint64_t)b * kPlanCandidates + j) * kPlanSums;
+      t += bs[0];
+      a += bs[1];
+      w += bs[2];
     }
     tt[j] = block_sum(t, lds);
     ta[j] = block_sum(a, lds);
+    tw[j] = block_sum(w, lds);
   }
   // Task size: the coarsest level in [min_j, max_j] that still yields
   // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
@@ -292,6 +304,10 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
   int jsel = -1;
   for (int j = want; j < kPlanCandidates && jsel < 0; ++j)
     if (tt[j] <= cap_tasks && ta[j] <= cap_accs) jsel = j;
+  // Buckets of about equal work: at most kMaxBuckets of `bucket` bytes.
+  const uint64_t total_work = jsel >= 0 ? tw[jsel] : 0;
+  uint64_t bucket = (total_work + kMaxBuckets - 1) / kMaxBuckets;
+  if (bucket < kMinBucketBytes) bucket = kMinBucketBytes;
   if (blockIdx.x == 0 && tid == 0) {
     ctl[kCtlNext] = 0;
     ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
@@ -299,43 +315,63 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     ctl[kCtlError] = jsel >= 0 ? 0 : 1;
   }
   if (jsel < 0) return;  // uniform over the grid
-  // Tasks and accumulators of the blocks before this one.
-  uint64_t pt = 0, pa = 0;
+  // Tasks, accumulators and work of the blocks before this one.
+  uint64_t pt = 0, pa = 0, pw = 0;
   for (uint32_t b = tid; b < blockIdx.x; b += kPlanThreads) {
-    pt += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel];
-    pa += block_sums[(uint64_t)b * 2 * kPlanCandidates + 2 * jsel + 1];
+    const uint64_t* bs = block_sums + ((uint64_t)b * kPlanCandidates + jsel) * kPlanSums;
+    pt += bs[0];
+    pa += bs[1];
+    pw += bs[2];
   }
   const uint64_t task_base = block_sum(pt, lds);
   const uint64_t acc_base = block_sum(pa, lds);
+  const uint64_t work_base = block_sum(pw, lds);
 
   const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + tid * kPlanPer;
-  uint64_t tk[kPlanPer], ac[kPlanPer];
-  uint64_t st = 0, sa = 0;
+  uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
+  uint64_t st = 0, sa = 0, sw = 0;
   for (int i = 0; i < kPlanPer; ++i) {
-    tk[i] = ac[i] = 0;
-    if (base + i < count) plan_counts(lengths[base + i] / exec_bytes, jsel, tk[i], ac[i]);
+    tk[i] = ac[i] = wk[i] = 0;
+    if (base + i < count) {
+      const uint64_t L = lengths[base + i];
+      plan_counts(L / exec_bytes, jsel, tk[i], ac[i]);
+      wk[i] = L + kTaskOverheadBytes * tk[i];
+    }
     st += tk[i];
     sa += ac[i];
+    sw += wk[i];
   }
-  uint64_t blk_t, blk_a;
+  uint64_t blk_t, blk_a, blk_w;
   const uint64_t et = block_exclusive(st, lds, blk_t);
   const uint64_t ea = block_exclusive(sa, lds, blk_a);
-  uint64_t run_t = task_base + et, run_a = acc_base + ea;
+  const uint64_t ew = block_exclusive(sw, lds, blk_w);
+  uint64_t run_t = task_base + et, run_a = acc_base + ea, run_w = work_base + ew;
   uint64_t loc = et;
   for (int i = 0; i < kPlanPer; ++i) {
     if (base + i < count) {
       task_start[base + i] = (uint32_t)run_t;
       acc_start[base + i] = (uint32_t)run_a;
     }
+    wstart[tid * kPlanPer + i] = run_w;  // work before this string
     run_t += tk[i];
     run_a += ac[i];
+    run_w += wk[i];
     loc += tk[i];
     incl[tid * kPlanPer + i] = (uint32_t)loc;  // inclusive task count inside the block
   }
   __syncthreads();
-  // fill the task -> string table for the tasks of this block's strings
+  // Fill the task -> string table for this block's tasks.  A task leads a
+  // bucket when a bucket boundary k * bucket falls in (start of the task
+  // before it, its own start]: the buckets are the runs of tasks from one
+  // leader to the next, each starting at the first task that begins at or
+  // after a boundary, so no bucket is empty.  Leaders carry bit 31 in the
+  // table and are appended to bucket_lead (in no particular order) with one
+  // atomic per workgroup.
   const uint64_t first = (uint64_t)blockIdx.x * kPlanBlock;
   const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
+  const uint64_t texec = 128ull << (3 * jsel);
+  const uint64_t unit = texec * exec_bytes + kTaskOverheadBytes;  // work of a full task
+  uint32_t nlead = 0;
   for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
     int lo = 0, hi = nstr - 1;  // first string whose inclusive count exceeds e
     while (lo < hi) {
@@ -343,7 +379,36 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
       if ((uint64_t)incl[mid] > e) hi = mid;
       else lo = mid + 1;
     }
-    task_string[task_base + e] = (uint32_t)(first + lo);
+    const uint64_t task = task_base + e;
+    const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
+    const uint64_t w0 = wstart[lo] + tau * unit;
+    bool lead = task == 0;
+    if (!lead) {
+      uint64_t wprev;  // start of the task before this one
+      if (tau > 0) {
+        wprev = w0 - unit;
+      } else {
+        // last task of the previous string (possibly another workgroup's)
+        const uint64_t Lp = lengths[first + lo - 1];
+        uint64_t ntp, nap;
+        plan_counts(Lp / exec_bytes, jsel, ntp, nap);
+        wprev = w0 - (Lp + kTaskOverheadBytes * ntp - (ntp - 1) * unit);
+      }
+      lead = w0 / bucket > wprev / bucket;
+    }
+    task_string[task] = (uint32_t)(first + lo) | (lead ? 0x80000000u : 0u);
+    nlead += lead;
+  }
+  // positions in bucket_lead: one atomic per workgroup
+  uint64_t blk_lead;
+  const uint64_t before = block_exclusive(nlead, lds, blk_lead);
+  __shared__ uint32_t lead_base;
+  if (tid == 0) lead_base = blk_lead ? atomicAdd(ctl + kCtlBuckets, (uint32_t)blk_lead) : 0;
+  __syncthreads();
+  uint32_t at = lead_base + (uint32_t)before;
+  for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
+    const uint64_t task = task_base + e;
+    if (task_string[task] >> 31) bucket_lead[at++] = (uint32_t)task;
   }
 }
 
@@ -468,7 +533,7 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
 }
 
 template <int WIDTH>
-__global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void hash_main_kernel(MainArgs a) {
   using Fm = Family<WIDTH>;
   using Ly = Layout<WIDTH>;
   constexpr int K = Fm::K;
@@ -477,7 +542,7 @@ __global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
 
   const int lane = threadIdx.x;
   const int q = lane >> 2, r = lane & 3;
-  const uint32_t total = uniform(a.ctl[kCtlTotal]);
+  const uint32_t nb = uniform(a.ctl[kCtlBuckets]);
   const uint32_t jlev = uniform(a.ctl[kCtlLevel]);
   const uint64_t texec = 128ull << (3 * jlev);
   const uint64_t* __restrict__ ent = a.ent;
@@ -489,13 +554,25 @@ __global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
       for (int t = 0; t < K; ++t) lacc[li][t][2 * lane] = lacc[li][t][2 * lane + 1] = 0;
   }
 
+  // Whole buckets from one counter: a bucket runs from its leader task up
+  // to the next leader (bit 31 of the task table) or the last task; a wave
+  // leaves once the counter ran past the last bucket.
+  const uint32_t ntasks_all = uniform(a.ctl[kCtlTotal]);
+  uint32_t task = 0;
+  bool fetch = true;
   for (;;) {
     __builtin_amdgcn_wave_barrier();
-    uint32_t task = 0;
-    if (lane == 0) task = atomicAdd(a.ctl + kCtlNext, 1u);
-    task = uniform(task);
-    if (task >= total) break;
-    const uint32_t s = uniform(a.task_string[task]);
+    if (fetch) {
+      uint32_t k = 0;
+      if (lane == 0) k = atomicAdd(a.ctl + kCtlNext, 1u);
+      k = uniform(k);
+      if (k >= nb) break;
+      task = uniform(a.bucket_lead[k]);
+      fetch = false;
+    }
+    const uint32_t s = uniform(a.task_string[task]) & 0x7FFFFFFFu;
+    // next task's entry, read early: whether it leads another bucket
+    const uint32_t next_entry = task + 1 < ntasks_all ? uniform(a.task_string[task + 1]) : 0x80000000u;
     const uint64_t tau = task - uniform(a.task_start[s]);
     const uint64_t off = uniform64(a.offsets[s]);
     const uint64_t L = uniform64(a.lengths[s]);
@@ -655,7 +732,9 @@ __global__ __launch_bounds__(64) void hash_main_kernel(MainArgs a) {
         }
       }
     }
-    // every lane finishes the task here, before the next one is fetched
+    // every lane finishes the task here, before the next one starts
+    ++task;
+    fetch = (next_entry >> 31) != 0;
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -695,12 +774,12 @@ uint64_t entropy_words_total() { return kEntropyWords; }
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const uint32_t nblocks = (uint32_t)((p.count + kPlanBlock - 1) / kPlanBlock);
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.block_sums);
+                     p.exec_bytes, p.block_sums, p.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
                      p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
-                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.ctl);
+                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.ctl);
   return hipGetLastError();
 }
 

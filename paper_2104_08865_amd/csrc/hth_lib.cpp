@@ -14,9 +14,11 @@
 #include <vector>
 
 #include "../../include/hth.h"
+#include "hth_host.h"
 #include "hth_kernels.h"
 
-namespace {
+namespace hth {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -47,25 +49,6 @@ void splitmix64_fill(uint64_t state, uint64_t* out, size_t n) {
     out[i] = z ^ (z >> 31);
   }
 }
-
-// Workspace of one (device, stream): planning arrays and the cross-task
-// accumulators.  sacc, sdone, gacc and gcnt hold zeros between launches (the
-// kernel that consumes an accumulator resets it), so a workspace is cleared
-// only once, when it is allocated.
-struct Workspace {
-  uint64_t cap_count = 0, cap_tasks = 0, cap_accs = 0, cap_blocks = 0;
-  void* mem = nullptr;
-  size_t bytes = 0;
-  uint32_t* ctl = nullptr;
-  uint64_t* block_sums = nullptr;
-  uint32_t* task_string = nullptr;
-  uint32_t* task_start = nullptr;
-  uint32_t* acc_start = nullptr;
-  uint64_t* sacc = nullptr;
-  uint32_t* sdone = nullptr;
-  uint64_t* gacc = nullptr;
-  uint32_t* gcnt = nullptr;
-};
 
 struct Tuning {
   uint32_t waves_per_cu = 0;
@@ -103,10 +86,11 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
     return at;
   };
   size_t o_ctl = take(hth::kCtlWords * 4);
-  size_t o_bs = take(n.cap_blocks * 2 * hth::kPlanCandidates * 8);
+  size_t o_bs = take(n.cap_blocks * hth::kPlanSums * hth::kPlanCandidates * 8);
   size_t o_ts = take(n.cap_tasks * 4);
   size_t o_st = take(n.cap_count * 4);
   size_t o_as = take(n.cap_count * 4);
+  size_t o_bf = take(((size_t)hth::kMaxBuckets + 2) * 4);
   size_t o_sacc = take(n.cap_count * hth::kMaxK * 8);
   size_t o_sdone = take(n.cap_count * 4);
   size_t o_gacc = take(n.cap_accs * hth::kMaxK * 8 * 8);
@@ -126,6 +110,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   n.task_string = reinterpret_cast<uint32_t*>(b + o_ts);
   n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
   n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
+  n.bucket_lead = reinterpret_cast<uint32_t*>(b + o_bf);
   n.sacc = reinterpret_cast<uint64_t*>(b + o_sacc);
   n.sdone = reinterpret_cast<uint32_t*>(b + o_sdone);
   n.gacc = reinterpret_cast<uint64_t*>(b + o_gacc);
@@ -189,13 +174,99 @@ hth_status grid_for(uint32_t width, uint32_t* grid) {
   return HTH_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace hth
 
-struct hth_seed {
-  int device = 0;
-  uint64_t* d_words = nullptr;
-  std::vector<uint64_t> host;
+struct hth_batch_graph {
+  hth::host::Workspace ws;  // private: replays of one graph must not overlap
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
+
+namespace hth {
+namespace host {
+
+hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                            const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width) {
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_hash_batch: out_width %u is not 16/24/32/40", out_width);
+  if (!seed) return fail(HTH_E_INVALID, "hth_hash_batch: seed is null");
+  if (count == 0) return HTH_OK;
+  if (!bytes || !offsets || !lengths || !out) return fail(HTH_E_INVALID, "hth_hash_batch: null pointer");
+  if (count > (1ull << 31)) return fail(HTH_E_INVALID, "hth_hash_batch: count %llu exceeds 2^31", (unsigned long long)count);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != seed->device) return fail(HTH_E_INVALID, "hth_hash_batch: seed lives on device %d, current is %d", seed->device, dev);
+  return HTH_OK;
+}
+
+// Planner and hashing kernel of one batch on `stream`, using workspace `w`.
+hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                         const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop) {
+  uint32_t grid = 0;
+  hth_status st = grid_for(out_width, &grid);
+  if (st != HTH_OK) return st;
+  Tuning tune;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    tune = g_tune[width_index(out_width)];
+  }
+  hth::PlanArgs p{};
+  p.lengths = lengths;
+  p.count = count;
+  p.exec_bytes = hth::exec_bytes_of(out_width);
+  p.block_sums = w.block_sums;
+  p.cap_tasks = w.cap_tasks;
+  p.cap_accs = w.cap_accs;
+  p.min_j = tune.min_j;
+  p.max_j = tune.max_j;
+  p.target_tasks = (uint64_t)grid * kTasksPerWave;
+  p.task_string = w.task_string;
+  p.task_start = w.task_start;
+  p.acc_start = w.acc_start;
+  p.bucket_lead = w.bucket_lead;
+  p.ctl = w.ctl;
+  hipError_t e = hth::launch_plan(p, stream);
+  if (e != hipSuccess) return hip_fail(e, "plan launch");
+
+  hth::MainArgs a{};
+  a.bytes = bytes;
+  a.offsets = offsets;
+  a.lengths = lengths;
+  a.out = out;
+  a.ent = seed->d_words + hth::entropy_offset_of(out_width);
+  a.task_string = w.task_string;
+  a.task_start = w.task_start;
+  a.acc_start = w.acc_start;
+  a.sacc = w.sacc;
+  a.sdone = w.sdone;
+  a.gacc = w.gacc;
+  a.gcnt = w.gcnt;
+  a.bucket_lead = w.bucket_lead;
+  a.ctl = w.ctl;
+  if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
+  e = hth::launch_main(out_width, a, grid, stream);
+  if (e != hipSuccess) return hip_fail(e, "main launch");
+  if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
+  return HTH_OK;
+}
+
+// Synchronise and read a workspace's planner status word.
+hth_status check_ctl(uint32_t* ctl, hipStream_t stream) {
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+  uint32_t err = 0;
+  e = hipMemcpy(&err, ctl + hth::kCtlError, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  if (err) return fail(HTH_E_TOO_LARGE, "the last batch exceeded the workspace plan limits");
+  return HTH_OK;
+}
+
+}  // namespace host
+}  // namespace hth
+
+using namespace hth::host;
 
 extern "C" {
 
@@ -288,63 +359,82 @@ hth_status hth_hash_batch(const hth_seed* seed, const uint8_t* bytes, const uint
 hth_status hth_hash_batch_timed(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                                 const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width,
                                 hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop) {
-  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_hash_batch: out_width %u is not 16/24/32/40", out_width);
-  if (!seed) return fail(HTH_E_INVALID, "hth_hash_batch: seed is null");
-  if (count == 0) return HTH_OK;
-  if (!bytes || !offsets || !lengths || !out) return fail(HTH_E_INVALID, "hth_hash_batch: null pointer");
-  if (count > (1ull << 31)) return fail(HTH_E_INVALID, "hth_hash_batch: count %llu exceeds 2^31", (unsigned long long)count);
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev != seed->device) return fail(HTH_E_INVALID, "hth_hash_batch: seed lives on device %d, current is %d", seed->device, dev);
-
+  hth_status st = check_batch_args(seed, bytes, offsets, lengths, count, out, out_width);
+  if (st != HTH_OK || count == 0) return st;
   Workspace* w = nullptr;
-  hth_status st = get_ws(count, stream, &w);
+  st = get_ws(count, stream, &w);
   if (st != HTH_OK) return st;
+  return enqueue_batch(seed, bytes, offsets, lengths, count, out, out_width, *w, stream, main_start, main_stop);
+}
+
+hth_status hth_batch_graph_create(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
+                                  const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width,
+                                  hth_batch_graph** graph) {
+  if (!graph) return fail(HTH_E_INVALID, "hth_batch_graph_create: graph is null");
+  *graph = nullptr;
+  hth_status st = check_batch_args(seed, bytes, offsets, lengths, count, out, out_width);
+  if (st != HTH_OK) return st;
+  if (count == 0) return fail(HTH_E_INVALID, "hth_batch_graph_create: count is 0");
   uint32_t grid = 0;
-  st = grid_for(out_width, &grid);
+  st = grid_for(out_width, &grid);  // fills the cache outside the capture
   if (st != HTH_OK) return st;
-  Tuning tune;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    tune = g_tune[width_index(out_width)];
+  hth_batch_graph* g = new (std::nothrow) hth_batch_graph;
+  if (!g) return fail(HTH_E_OOM, "hth_batch_graph_create: host allocation");
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "capture stream");
   }
+  st = ws_alloc(g->ws, count, cs);
+  if (st == HTH_OK) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "hipStreamBeginCapture");
+    } else {
+      st = enqueue_batch(seed, bytes, offsets, lengths, count, out, out_width, g->ws, cs, nullptr, nullptr);
+      hipGraph_t graph_obj = nullptr;
+      e = hipStreamEndCapture(cs, &graph_obj);  // always end the capture
+      if (st == HTH_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+      g->graph = graph_obj;
+      if (st == HTH_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+      }
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != HTH_OK) {
+    hth_batch_graph_free(g);
+    return st;
+  }
+  *graph = g;
+  return HTH_OK;
+}
 
-  hth::PlanArgs p{};
-  p.lengths = lengths;
-  p.count = count;
-  p.exec_bytes = hth::exec_bytes_of(out_width);
-  p.block_sums = w->block_sums;
-  p.cap_tasks = w->cap_tasks;
-  p.cap_accs = w->cap_accs;
-  p.min_j = tune.min_j;
-  p.max_j = tune.max_j;
-  p.target_tasks = (uint64_t)grid * kTasksPerWave;
-  p.task_string = w->task_string;
-  p.task_start = w->task_start;
-  p.acc_start = w->acc_start;
-  p.ctl = w->ctl;
-  e = hth::launch_plan(p, stream);
-  if (e != hipSuccess) return hip_fail(e, "plan launch");
+hth_status hth_batch_graph_launch(hth_batch_graph* graph, hipStream_t stream) {
+  if (!graph || !graph->exec) return fail(HTH_E_INVALID, "hth_batch_graph_launch: graph is null");
+  hipError_t e = hipGraphLaunch(graph->exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return HTH_OK;
+}
 
-  hth::MainArgs a{};
-  a.bytes = bytes;
-  a.offsets = offsets;
-  a.lengths = lengths;
-  a.out = out;
-  a.ent = seed->d_words + hth::entropy_offset_of(out_width);
-  a.task_string = w->task_string;
-  a.task_start = w->task_start;
-  a.acc_start = w->acc_start;
-  a.sacc = w->sacc;
-  a.sdone = w->sdone;
-  a.gacc = w->gacc;
-  a.gcnt = w->gcnt;
-  a.ctl = w->ctl;
-  if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
-  e = hth::launch_main(out_width, a, grid, stream);
-  if (e != hipSuccess) return hip_fail(e, "main launch");
-  if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
+hth_status hth_batch_graph_check(hth_batch_graph* graph, hipStream_t stream) {
+  if (!graph) return fail(HTH_E_INVALID, "hth_batch_graph_check: graph is null");
+  return check_ctl(graph->ws.ctl, stream);
+}
+
+hth_status hth_batch_graph_free(hth_batch_graph* graph) {
+  if (!graph) return HTH_OK;
+  hipError_t e = hipSuccess;
+  if (graph->exec) e = hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  if (graph->ws.mem) {
+    hipError_t f = hipFree(graph->ws.mem);
+    if (e == hipSuccess) e = f;
+  }
+  delete graph;
+  if (e != hipSuccess) return hip_fail(e, "hth_batch_graph_free");
   return HTH_OK;
 }
 
@@ -359,13 +449,7 @@ hth_status hth_batch_check(hipStream_t stream) {
     if (it == g_ws.end()) return HTH_OK;
     ctl = it->second.ctl;
   }
-  e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return hip_fail(e, "stream synchronise");
-  uint32_t err = 0;
-  e = hipMemcpy(&err, ctl + hth::kCtlError, 4, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "status read");
-  if (err) return fail(HTH_E_TOO_LARGE, "the last batch on this stream exceeded the workspace plan limits");
-  return HTH_OK;
+  return check_ctl(ctl, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,621 @@
+// libhth serving loop (hth_serve_* of include/hth.h): requests of host bytes
+// are admitted by device memory, gathered into batches as they arrive and
+// hashed by the same planner and kernel as hth_hash_batch.  This file only
+// moves bytes, schedules batches and tracks tickets; every hash value comes
+// from the HIP kernels.
+//
+// Data path of one request:
+//   submit:  bytes copied into a pinned host ring (FIFO allocation);
+//   worker:  admitted when the device ring (the memory budget) has room,
+//            packed with the other admitted requests into a batch, copied
+//            host ring -> device ring on the batch's stream, hashed (one
+//            launch per output width present), results copied back to a
+//            pinned buffer;
+//   retire:  when the batch's event completes, results move to the ticket
+//            table, both ring regions are released and latencies recorded.
+// Batches go to `slots` streams round robin, so the copies of one batch
+// overlap the hashing of another.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hth_host.h"
+
+using namespace hth::host;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;  // request bytes start on 256-byte boundaries in both rings
+constexpr uint64_t kDefaultDevice = 1ull << 30;
+constexpr uint64_t kDefaultStage = 1ull << 30;
+constexpr uint64_t kDefaultRequest = 16ull << 20;
+constexpr uint64_t kDefaultBatchBytes = 64ull << 20;
+constexpr uint32_t kDefaultBatchRequests = 16384;
+constexpr uint32_t kDefaultSlots = 3;
+constexpr uint32_t kDefaultOutstanding = 1u << 20;
+constexpr uint32_t kMaxSlots = 8;
+constexpr uint32_t kMaxBatchRequests = 1u << 22;
+constexpr uint32_t kMaxOutstanding = 1u << 24;
+// The planner's workspace always fits a batch of up to this many bytes (its
+// task table holds 2^19 tasks beyond one per string).
+constexpr uint64_t kMaxBatchBytes = 1ull << 36;
+constexpr int kWidths = 4;
+
+uint64_t pad(uint64_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
+int widx(uint32_t w) { return (int)(w / 8) - 2; }
+
+// FIFO allocator over a ring of `cap` bytes.  Positions grow without bound;
+// an allocation never straddles the end of the ring (it moves to the next
+// start instead); space is released in allocation order.
+struct Ring {
+  uint64_t cap = 0, head = 0, tail = 0;
+  bool alloc(uint64_t n, uint64_t* pos) {
+    uint64_t p = head;
+    const uint64_t at = p % cap;
+    if (at + n > cap) p += cap - at;
+    if (p + n - tail > cap) return false;
+    head = p + n;
+    *pos = p;
+    return true;
+  }
+};
+
+struct Request {
+  uint64_t ticket;
+  uint64_t host_pos, dev_pos;
+  uint64_t len;
+  uint32_t width;
+  bool deferred;
+  Clock::time_point t_submit;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  Workspace ws;
+  uint64_t* h_meta = nullptr;  // pinned: per width, offsets then lengths
+  uint64_t* d_meta = nullptr;
+  uint8_t* h_out = nullptr;  // pinned results, grouped by width
+  uint8_t* d_out = nullptr;
+  std::vector<Request> reqs;
+  uint64_t out_at[kWidths] = {};  // byte offset of each width group in the results
+  uint64_t host_end = 0, dev_end = 0;
+  bool busy = false;
+};
+
+enum : uint8_t { kFree = 0, kPending = 1, kReady = 2 };
+
+struct Entry {
+  uint64_t ticket = 0;
+  uint8_t state = kFree;
+  uint8_t width = 0;
+  uint8_t out[40];
+};
+
+}  // namespace
+
+struct hth_server {
+  hth_serve_config cfg{};
+  const hth_seed* seed = nullptr;
+  int device = 0;
+
+  uint8_t* h_ring = nullptr;
+  uint8_t* d_ring = nullptr;
+  std::vector<Slot> slots;
+
+  // submitters: one at a time (FIFO order of the host ring = queue order)
+  std::mutex submit_mu;
+  // host ring and pending queue
+  std::mutex q_mu;
+  std::condition_variable q_cv;
+  Ring host;
+  std::deque<Request> pending;
+  uint64_t next_ticket = 1;
+
+  Ring dev;  // worker only
+  uint32_t next_slot = 0;
+  std::deque<uint32_t> inflight;  // slot indices in launch order
+
+  // tickets
+  std::mutex r_mu;
+  std::condition_variable r_cv;
+  std::vector<Entry> entries;
+  uint64_t mask = 0;
+
+  // statistics since the last reset (under r_mu)
+  std::vector<float> lat_us;
+  uint64_t n_submitted = 0, n_completed = 0, n_deferred = 0, n_busy = 0, n_batches = 0, n_batch_reqs = 0,
+           n_bytes = 0;
+  bool have_first = false;
+  Clock::time_point t_first, t_last;
+
+  std::atomic<bool> stop{false};
+  std::atomic<bool> paused{false};
+  std::atomic<int> failed{0};
+  std::string fail_msg;  // written once, before `failed` is set
+  std::thread worker;
+};
+
+namespace {
+
+hth_status server_error(hth_server* s) {
+  return fail(HTH_E_HIP, "serving loop stopped after an error: %s", s->fail_msg.c_str());
+}
+
+void set_failed(hth_server* s, hipError_t e, const char* what) {
+  if (s->failed.load()) return;
+  s->fail_msg = std::string(what) + ": " + hipGetErrorString(e);
+  s->failed.store(1);
+  s->q_cv.notify_all();
+  std::lock_guard<std::mutex> lk(s->r_mu);
+  s->r_cv.notify_all();
+}
+
+// Moves admitted requests from the queue into slot `si` and enqueues the
+// batch.  Returns false when nothing was admitted.
+bool launch_batch(hth_server* s, uint32_t si) {
+  Slot& sl = s->slots[si];
+  sl.reqs.clear();
+  uint64_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    while (!s->pending.empty() && sl.reqs.size() < s->cfg.max_batch_requests) {
+      Request& r = s->pending.front();
+      if (!sl.reqs.empty() && bytes + r.len > s->cfg.max_batch_bytes) break;
+      uint64_t pos = 0;
+      if (!s->dev.alloc(pad(r.len), &pos)) {
+        // device budget exhausted: the request waits for a batch to retire
+        if (!r.deferred) {
+          r.deferred = true;
+          std::lock_guard<std::mutex> rl(s->r_mu);
+          ++s->n_deferred;
+        }
+        break;
+      }
+      r.dev_pos = pos;
+      bytes += r.len;
+      sl.reqs.push_back(r);
+      s->pending.pop_front();
+    }
+  }
+  if (sl.reqs.empty()) return false;
+  sl.host_end = sl.reqs.back().host_pos + pad(sl.reqs.back().len);
+  sl.dev_end = s->dev.head;
+
+  // group by width, in submission order inside each group
+  uint64_t n[kWidths] = {};
+  for (const Request& r : sl.reqs) ++n[widx(r.width)];
+  uint64_t meta_at[kWidths], out_at = 0, meta = 0;
+  for (int w = 0; w < kWidths; ++w) {
+    meta_at[w] = meta;
+    meta += 2 * n[w];
+    sl.out_at[w] = out_at;
+    out_at += n[w] * (uint64_t)(16 + 8 * w);
+  }
+  uint64_t fillw[kWidths] = {};
+  for (const Request& r : sl.reqs) {
+    const int w = widx(r.width);
+    sl.h_meta[meta_at[w] + fillw[w]] = r.dev_pos % s->dev.cap;
+    sl.h_meta[meta_at[w] + n[w] + fillw[w]] = r.len;
+    ++fillw[w];
+  }
+
+  hipError_t e = hipSuccess;
+  // request bytes: runs contiguous in both rings become one copy
+  size_t i = 0;
+  while (i < sl.reqs.size() && e == hipSuccess) {
+    const uint64_t h0 = sl.reqs[i].host_pos, d0 = sl.reqs[i].dev_pos;
+    uint64_t len = pad(sl.reqs[i].len);
+    size_t j = i + 1;
+    while (j < sl.reqs.size() && sl.reqs[j].host_pos == h0 + len && sl.reqs[j].dev_pos == d0 + len &&
+           (h0 % s->host.cap) + len + pad(sl.reqs[j].len) <= s->host.cap &&
+           (d0 % s->dev.cap) + len + pad(sl.reqs[j].len) <= s->dev.cap) {
+      len += pad(sl.reqs[j].len);
+      ++j;
+    }
+    if (len)
+      e = hipMemcpyAsync(s->d_ring + d0 % s->dev.cap, s->h_ring + h0 % s->host.cap, len, hipMemcpyHostToDevice,
+                         sl.stream);
+    i = j;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(sl.d_meta, sl.h_meta, meta * 8, hipMemcpyHostToDevice, sl.stream);
+  if (e != hipSuccess) {
+    set_failed(s, e, "batch upload");
+    return false;
+  }
+  for (int w = 0; w < kWidths; ++w) {
+    if (!n[w]) continue;
+    const uint64_t* d_off = sl.d_meta + meta_at[w];
+    hth_status st = enqueue_batch(s->seed, s->d_ring, d_off, d_off + n[w], n[w], sl.d_out + sl.out_at[w],
+                                  (uint32_t)(16 + 8 * w), sl.ws, sl.stream, nullptr, nullptr);
+    if (st != HTH_OK) {
+      set_failed(s, hipErrorLaunchFailure, "batch launch");
+      return false;
+    }
+  }
+  e = hipMemcpyAsync(sl.h_out, sl.d_out, out_at, hipMemcpyDeviceToHost, sl.stream);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+  if (e != hipSuccess) {
+    set_failed(s, e, "batch download");
+    return false;
+  }
+  sl.busy = true;
+  s->inflight.push_back(si);
+  return true;
+}
+
+// Publishes the results of the oldest batch if its event completed.
+bool retire_one(hth_server* s) {
+  if (s->inflight.empty()) return false;
+  Slot& sl = s->slots[s->inflight.front()];
+  hipError_t e = hipEventQuery(sl.done);
+  if (e == hipErrorNotReady) return false;
+  if (e != hipSuccess) {
+    set_failed(s, e, "batch completion");
+    return false;
+  }
+  const Clock::time_point now = Clock::now();
+  uint64_t fillw[kWidths] = {}, bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->r_mu);
+    for (const Request& r : sl.reqs) {
+      const int w = widx(r.width);
+      Entry& en = s->entries[r.ticket & s->mask];
+      std::memcpy(en.out, sl.h_out + sl.out_at[w] + fillw[w] * r.width, r.width);
+      ++fillw[w];
+      en.state = kReady;
+      s->lat_us.push_back((float)std::chrono::duration<double, std::micro>(now - r.t_submit).count());
+      bytes += r.len;
+    }
+    s->n_completed += sl.reqs.size();
+    s->n_bytes += bytes;
+    ++s->n_batches;
+    s->n_batch_reqs += sl.reqs.size();
+    s->t_last = now;
+    s->r_cv.notify_all();
+  }
+  s->dev.tail = sl.dev_end;
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->host.tail = sl.host_end;
+  }
+  s->q_cv.notify_all();  // submitters waiting for host ring space
+  sl.busy = false;
+  s->inflight.pop_front();
+  return true;
+}
+
+void worker_main(hth_server* s) {
+  if (hipSetDevice(s->device) != hipSuccess) {
+    set_failed(s, hipErrorInvalidDevice, "worker hipSetDevice");
+    return;
+  }
+  while (!s->stop.load() && !s->failed.load()) {
+    bool progress = false;
+    while (retire_one(s)) progress = true;
+    if (s->failed.load()) break;
+    Slot& next = s->slots[s->next_slot];
+    if (!next.busy && !s->paused.load()) {
+      bool have = false;
+      {
+        std::lock_guard<std::mutex> lk(s->q_mu);
+        have = !s->pending.empty();
+      }
+      if (have && launch_batch(s, s->next_slot)) {
+        s->next_slot = (s->next_slot + 1) % (uint32_t)s->slots.size();
+        progress = true;
+      }
+    }
+    if (progress) continue;
+    if (s->inflight.empty()) {
+      std::unique_lock<std::mutex> lk(s->q_mu);
+      s->q_cv.wait_for(lk, std::chrono::milliseconds(50),
+                       [&] { return s->stop.load() || (!s->pending.empty() && !s->paused.load()); });
+    } else {
+      std::this_thread::yield();  // a batch is in flight: poll its event
+    }
+  }
+  // drain what is in flight so that buffers are idle before destruction
+  for (uint32_t si : s->inflight) (void)hipEventSynchronize(s->slots[si].done);
+}
+
+void free_server(hth_server* s) {
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.ws.mem) (void)hipFree(sl.ws.mem);
+    if (sl.h_meta) (void)hipHostFree(sl.h_meta);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.d_meta) (void)hipFree(sl.d_meta);
+    if (sl.d_out) (void)hipFree(sl.d_out);
+  }
+  if (s->h_ring) (void)hipHostFree(s->h_ring);
+  if (s->d_ring) (void)hipFree(s->d_ring);
+  delete s;
+}
+
+hth_status take(hth_server* s, uint64_t ticket, uint8_t* out, bool block) {
+  std::unique_lock<std::mutex> lk(s->r_mu);
+  Entry& en = s->entries[ticket & s->mask];
+  if (en.ticket != ticket || en.state == kFree)
+    return fail(HTH_E_INVALID, "ticket %llu is unknown or already collected", (unsigned long long)ticket);
+  if (en.state == kPending) {
+    if (!block) {
+      if (s->failed.load()) return server_error(s);
+      return HTH_E_BUSY;
+    }
+    s->r_cv.wait(lk, [&] { return en.state == kReady || s->failed.load(); });
+    if (en.state != kReady) return server_error(s);
+  }
+  std::memcpy(out, en.out, en.width);
+  en.state = kFree;
+  return HTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed, hth_server** out) {
+  if (!out) return fail(HTH_E_INVALID, "hth_serve_create: out is null");
+  *out = nullptr;
+  if (!config) return fail(HTH_E_INVALID, "hth_serve_create: config is null");
+  hth_serve_config c = *config;
+  if (!c.max_device_bytes) c.max_device_bytes = kDefaultDevice;
+  if (!c.host_stage_bytes) c.host_stage_bytes = kDefaultStage;
+  if (!c.max_request_bytes) c.max_request_bytes = kDefaultRequest;
+  if (!c.max_batch_bytes) c.max_batch_bytes = kDefaultBatchBytes;
+  if (!c.max_batch_requests) c.max_batch_requests = kDefaultBatchRequests;
+  if (!c.slots) c.slots = kDefaultSlots;
+  if (!c.max_outstanding) c.max_outstanding = kDefaultOutstanding;
+  if (pad(c.max_request_bytes) > c.max_device_bytes || pad(c.max_request_bytes) > c.host_stage_bytes)
+    return fail(HTH_E_INVALID, "hth_serve_create: max_request_bytes %llu does not fit the device budget or staging",
+                (unsigned long long)c.max_request_bytes);
+  if (c.max_batch_bytes > kMaxBatchBytes)
+    return fail(HTH_E_INVALID, "hth_serve_create: max_batch_bytes above %llu", (unsigned long long)kMaxBatchBytes);
+  if (c.slots > kMaxSlots) return fail(HTH_E_INVALID, "hth_serve_create: slots %u above %u", c.slots, kMaxSlots);
+  if (c.max_batch_requests > kMaxBatchRequests)
+    return fail(HTH_E_INVALID, "hth_serve_create: max_batch_requests %u above %u", c.max_batch_requests,
+                kMaxBatchRequests);
+  if (c.max_outstanding > kMaxOutstanding)
+    return fail(HTH_E_INVALID, "hth_serve_create: max_outstanding %u above %u", c.max_outstanding, kMaxOutstanding);
+  uint32_t outstanding = 1;
+  while (outstanding < c.max_outstanding) outstanding <<= 1;
+  c.max_outstanding = outstanding;
+  if (!seed) return fail(HTH_E_INVALID, "hth_serve_create: seed is null");
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != seed->device)
+    return fail(HTH_E_INVALID, "hth_serve_create: seed lives on device %d, current is %d", seed->device, dev);
+
+  hth_server* s = new (std::nothrow) hth_server;
+  if (!s) return fail(HTH_E_OOM, "hth_serve_create: host allocation");
+  s->cfg = c;
+  s->seed = seed;
+  s->device = dev;
+  s->host.cap = c.host_stage_bytes;
+  s->dev.cap = c.max_device_bytes;
+  s->mask = outstanding - 1;
+  try {
+    s->entries.resize(outstanding);
+    s->slots.resize(c.slots);
+  } catch (...) {
+    delete s;
+    return fail(HTH_E_OOM, "hth_serve_create: host allocation");
+  }
+  hth_status st = HTH_OK;
+  const char* what = "";
+  e = hipHostMalloc((void**)&s->h_ring, c.host_stage_bytes, hipHostMallocDefault);
+  what = "staging ring";
+  if (e == hipSuccess) {
+    e = hipMalloc((void**)&s->d_ring, c.max_device_bytes);
+    what = "device ring";
+  }
+  const uint64_t meta_bytes = (uint64_t)c.max_batch_requests * 16;
+  const uint64_t out_bytes = (uint64_t)c.max_batch_requests * 40;
+  for (Slot& sl : s->slots) {
+    if (e != hipSuccess) break;
+    what = "slot buffers";
+    e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_meta, meta_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_out, out_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_meta, meta_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_out, out_bytes);
+    if (e == hipSuccess) {
+      st = ws_alloc(sl.ws, c.max_batch_requests, sl.stream);
+      if (st != HTH_OK) break;
+    }
+  }
+  if (e != hipSuccess) st = hip_fail(e, what);
+  if (st != HTH_OK) {
+    std::string msg = hth_last_error();
+    free_server(s);
+    return fail(st, "hth_serve_create: %s", msg.c_str());
+  }
+  try {
+    s->worker = std::thread(worker_main, s);
+  } catch (...) {
+    free_server(s);
+    return fail(HTH_E_OOM, "hth_serve_create: worker thread");
+  }
+  *out = s;
+  return HTH_OK;
+}
+
+hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len, uint32_t out_width,
+                            uint64_t* ticket) {
+  const Clock::time_point t0 = Clock::now();
+  if (!s || !ticket) return fail(HTH_E_INVALID, "hth_serve_submit: null server or ticket");
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_serve_submit: out_width %u", out_width);
+  if (len && !host_bytes) return fail(HTH_E_INVALID, "hth_serve_submit: host_bytes is null");
+  if (len > s->cfg.max_request_bytes)
+    return fail(HTH_E_TOO_LARGE, "hth_serve_submit: %llu bytes above the limit %llu", (unsigned long long)len,
+                (unsigned long long)s->cfg.max_request_bytes);
+  if (s->failed.load()) return server_error(s);
+  std::lock_guard<std::mutex> sub(s->submit_mu);
+  uint64_t t = 0, pos = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    t = s->next_ticket;
+    const uint64_t old_head = s->host.head;
+    bool ok = s->host.alloc(pad(len), &pos);
+    if (ok) {
+      std::lock_guard<std::mutex> rl(s->r_mu);
+      Entry& en = s->entries[t & s->mask];
+      if (en.state != kFree) {
+        ok = false;
+        s->host.head = old_head;  // undo: nothing was allocated after it
+      } else {
+        en.ticket = t;
+        en.state = kPending;
+        en.width = (uint8_t)out_width;
+        ++s->n_submitted;
+        if (!s->have_first) {
+          s->have_first = true;
+          s->t_first = t0;
+        }
+      }
+    }
+    if (!ok) {
+      std::lock_guard<std::mutex> rl(s->r_mu);
+      ++s->n_busy;
+      return HTH_E_BUSY;
+    }
+    ++s->next_ticket;
+  }
+  if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->pending.push_back(Request{t, pos, 0, len, out_width, false, t0});
+  }
+  s->q_cv.notify_all();
+  *ticket = t;
+  return HTH_OK;
+}
+
+hth_status hth_serve_poll(hth_server* s, uint64_t ticket, uint8_t* out_host) {
+  if (!s || !out_host) return fail(HTH_E_INVALID, "hth_serve_poll: null server or output");
+  return take(s, ticket, out_host, false);
+}
+
+hth_status hth_serve_wait(hth_server* s, uint64_t ticket, uint8_t* out_host) {
+  if (!s || !out_host) return fail(HTH_E_INVALID, "hth_serve_wait: null server or output");
+  return take(s, ticket, out_host, true);
+}
+
+hth_status hth_serve_wait_many(hth_server* s, const uint64_t* tickets, uint64_t n, uint8_t* out_host,
+                               uint32_t out_stride) {
+  if (!s || (n && (!tickets || !out_host))) return fail(HTH_E_INVALID, "hth_serve_wait_many: null pointer");
+  if (out_stride < 40) return fail(HTH_E_INVALID, "hth_serve_wait_many: out_stride %u below 40", out_stride);
+  for (uint64_t i = 0; i < n; ++i) {
+    hth_status st = take(s, tickets[i], out_host + i * out_stride, true);
+    if (st != HTH_OK) return st;
+  }
+  return HTH_OK;
+}
+
+hth_status hth_serve_replay(hth_server* s, const uint8_t* base, const uint64_t* offsets, const uint64_t* lengths,
+                            const uint32_t* widths, const uint64_t* arrival_ns, uint64_t n, uint64_t* tickets) {
+  if (!s || (n && (!base || !offsets || !lengths || !widths || !arrival_ns || !tickets)))
+    return fail(HTH_E_INVALID, "hth_serve_replay: null pointer");
+  const Clock::time_point t0 = Clock::now();
+  for (uint64_t i = 0; i < n; ++i) {
+    const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
+    while (Clock::now() < due) {
+    }
+    for (;;) {
+      hth_status st = hth_serve_submit(s, base + offsets[i], lengths[i], widths[i], tickets + i);
+      if (st == HTH_OK) break;
+      if (st != HTH_E_BUSY) return st;
+      std::this_thread::yield();  // staging full: wait for a batch to retire
+    }
+  }
+  return HTH_OK;
+}
+
+hth_status hth_serve_pause(hth_server* s, int32_t paused) {
+  if (!s) return fail(HTH_E_INVALID, "hth_serve_pause: null server");
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->paused.store(paused != 0);
+  }
+  s->q_cv.notify_all();
+  return HTH_OK;
+}
+
+hth_status hth_serve_stats(hth_server* s, hth_serve_report* out) {
+  if (!s || !out) return fail(HTH_E_INVALID, "hth_serve_stats: null pointer");
+  std::vector<float> lat;
+  hth_serve_report r{};
+  {
+    std::lock_guard<std::mutex> lk(s->r_mu);
+    lat = s->lat_us;
+    r.submitted = s->n_submitted;
+    r.completed = s->n_completed;
+    r.deferred = s->n_deferred;
+    r.busy = s->n_busy;
+    r.batches = s->n_batches;
+    r.bytes = s->n_bytes;
+    r.mean_batch_requests = s->n_batches ? (double)s->n_batch_reqs / (double)s->n_batches : 0.0;
+    if (s->have_first && s->n_completed)
+      r.elapsed_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
+  }
+  r.gbps = r.elapsed_s > 0 ? (double)r.bytes / r.elapsed_s / 1e9 : 0.0;
+  if (!lat.empty()) {
+    auto rank = [&](double q) {
+      size_t k = (size_t)(q * (double)(lat.size() - 1) + 0.5);
+      std::nth_element(lat.begin(), lat.begin() + k, lat.end());
+      return (double)lat[k];
+    };
+    double sum = 0;
+    float mx = 0;
+    for (float v : lat) {
+      sum += v;
+      mx = std::max(mx, v);
+    }
+    r.latency_mean_us = sum / (double)lat.size();
+    r.latency_max_us = mx;
+    r.latency_p50_us = rank(0.50);
+    r.latency_p99_us = rank(0.99);
+  }
+  *out = r;
+  if (s->failed.load()) return server_error(s);
+  return HTH_OK;
+}
+
+hth_status hth_serve_reset_stats(hth_server* s) {
+  if (!s) return fail(HTH_E_INVALID, "hth_serve_reset_stats: null server");
+  std::lock_guard<std::mutex> lk(s->r_mu);
+  s->lat_us.clear();
+  s->n_submitted = s->n_completed = s->n_deferred = s->n_busy = s->n_batches = s->n_batch_reqs = s->n_bytes = 0;
+  s->have_first = false;
+  return HTH_OK;
+}
+
+hth_status hth_serve_destroy(hth_server* s) {
+  if (!s) return HTH_OK;
+  s->stop.store(true);
+  s->q_cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  const bool was_failed = s->failed.load() != 0;
+  std::string msg = s->fail_msg;
+  free_server(s);
+  if (was_failed) return fail(HTH_E_HIP, "serving loop had stopped after an error: %s", msg.c_str());
+  return HTH_OK;
+}
+
+}  // extern "C"

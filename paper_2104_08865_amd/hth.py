@@ -26,8 +26,31 @@ WIDTHS = (16, 24, 32, 40)
 SYMBOLS = (
     "hth_last_error", "hth_entropy_words", "hth_expand_seed", "hth_seed_from_entropy",
     "hth_seed_entropy", "hth_seed_free", "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve",
-    "hth_batch_check", "hth_set_tuning",
+    "hth_batch_check", "hth_set_tuning", "hth_batch_graph_create", "hth_batch_graph_launch",
+    "hth_batch_graph_check", "hth_batch_graph_free", "hth_serve_create", "hth_serve_submit",
+    "hth_serve_poll", "hth_serve_wait", "hth_serve_wait_many", "hth_serve_replay", "hth_serve_stats",
+    "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause",
 )
+
+
+class ServeConfig(ctypes.Structure):
+    """hth_serve_config (zero fields take the library's defaults)."""
+    _fields_ = [("max_device_bytes", ctypes.c_uint64), ("host_stage_bytes", ctypes.c_uint64),
+                ("max_request_bytes", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
+                ("max_batch_requests", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("max_outstanding", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ServeReport(ctypes.Structure):
+    """hth_serve_report."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("busy", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("elapsed_s", ctypes.c_double), ("gbps", ctypes.c_double), ("latency_p50_us", ctypes.c_double),
+                ("latency_p99_us", ctypes.c_double), ("latency_max_us", ctypes.c_double),
+                ("latency_mean_us", ctypes.c_double), ("mean_batch_requests", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 _lib = None
 
@@ -59,8 +82,26 @@ def lib():
         L.hth_reserve.argtypes = [u64, vp]
         L.hth_batch_check.argtypes = [vp]
         L.hth_set_tuning.argtypes = [u32, u32, u32, u32]
+        L.hth_batch_graph_create.argtypes = [vp, vp, vp, vp, u64, vp, u32, ctypes.POINTER(vp)]
+        L.hth_batch_graph_launch.argtypes = [vp, vp]
+        L.hth_batch_graph_check.argtypes = [vp, vp]
+        L.hth_batch_graph_free.argtypes = [vp]
+        L.hth_serve_create.argtypes = [ctypes.POINTER(ServeConfig), vp, ctypes.POINTER(vp)]
+        L.hth_serve_submit.argtypes = [vp, vp, u64, u32, ctypes.POINTER(u64)]
+        L.hth_serve_poll.argtypes = [vp, u64, vp]
+        L.hth_serve_wait.argtypes = [vp, u64, vp]
+        L.hth_serve_wait_many.argtypes = [vp, vp, u64, vp, u32]
+        L.hth_serve_replay.argtypes = [vp, vp, vp, vp, vp, vp, u64, vp]
+        L.hth_serve_stats.argtypes = [vp, ctypes.POINTER(ServeReport)]
+        L.hth_serve_reset_stats.argtypes = [vp]
+        L.hth_serve_destroy.argtypes = [vp]
+        L.hth_serve_pause.argtypes = [vp, ctypes.c_int32]
+        for name in SYMBOLS[2:]:
+            getattr(L, name).restype = ctypes.c_int32
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
-                     "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning"):
+                     "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning",
+                     "hth_batch_graph_create", "hth_batch_graph_launch", "hth_batch_graph_check",
+                     "hth_batch_graph_free"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -190,3 +231,136 @@ def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None, t
     else:
         _check(lib().hth_hash_batch_timed(*args, timer.start, timer.stop))
     return out
+
+
+class BatchGraph:
+    """A captured hth_hash_batch (planner + hashing kernel) for repeated launches.
+
+    The tensors passed here must stay alive (and keep their storage) as long
+    as the graph is used; their contents may change between launches."""
+
+    def __init__(self, seed, data, offsets, lengths, out_width, out=None):
+        import torch
+        count = offsets.numel()
+        if out is None:
+            out = torch.empty((count, out_width), dtype=torch.uint8, device=data.device)
+        self.out = out
+        self._keep = (seed, data, offsets, lengths)
+        h = ctypes.c_void_p()
+        dp = data.data_ptr() if data.numel() else offsets.data_ptr()
+        _check(lib().hth_batch_graph_create(seed.handle, ctypes.c_void_p(dp), ctypes.c_void_p(offsets.data_ptr()),
+                                            ctypes.c_void_p(lengths.data_ptr()), count,
+                                            ctypes.c_void_p(out.data_ptr()), out_width, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().hth_batch_graph_launch(self._h, _stream(stream)))
+        return self.out
+
+    def check(self, stream=None):
+        _check(lib().hth_batch_graph_check(self._h, _stream(stream)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            lib().hth_batch_graph_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving loop (hth_serve_*): submit host byte strings, collect hashes.
+
+    Requests are admitted by device memory and batched on the GPU as they
+    arrive; results equal hth_hash_batch's for the same bytes and width."""
+
+    def __init__(self, seed, **config):
+        self._seed = seed  # the server reads the seed's device words
+        cfg = ServeConfig(**config)
+        h = ctypes.c_void_p()
+        _check(lib().hth_serve_create(ctypes.byref(cfg), seed.handle, ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, data, out_width):
+        """Submit bytes (bytes, bytearray or a uint8 numpy array); returns
+        the ticket, or None when the server is busy (staging full or too
+        many uncollected results)."""
+        buf = np.ascontiguousarray(np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray))
+                                   else data, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        rc = lib().hth_serve_submit(self._h, ctypes.c_void_p(buf.ctypes.data if buf.size else 0), buf.size,
+                                    out_width, ctypes.byref(t))
+        if rc == HTH_E_BUSY:
+            return None
+        _check(rc)
+        return t.value
+
+    def poll(self, ticket):
+        """The result bytes if ready, else None."""
+        out = (ctypes.c_uint8 * 40)()
+        rc = lib().hth_serve_poll(self._h, ticket, out)
+        if rc == HTH_E_BUSY:
+            return None
+        _check(rc)
+        return bytes(out)
+
+    def wait(self, ticket, out_width):
+        out = (ctypes.c_uint8 * 40)()
+        _check(lib().hth_serve_wait(self._h, ticket, out))
+        return bytes(out)[:out_width]
+
+    def wait_many(self, tickets):
+        """Results of many tickets as an (n, 40) uint8 array (a row holds
+        its request's out_width bytes, then zeros)."""
+        t = np.ascontiguousarray(tickets, dtype=np.uint64)
+        out = np.zeros((t.size, 40), dtype=np.uint8)
+        _check(lib().hth_serve_wait_many(self._h, ctypes.c_void_p(t.ctypes.data), t.size,
+                                         ctypes.c_void_p(out.ctypes.data), 40))
+        return out
+
+    def replay(self, base, offsets, lengths, widths, arrival_ns):
+        """Submit request i (base[offsets[i]:][:lengths[i]], widths[i]) at
+        arrival_ns[i] after the call starts; returns the tickets."""
+        base = np.ascontiguousarray(base, dtype=np.uint8)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = np.ascontiguousarray(lengths, dtype=np.uint64)
+        w = np.ascontiguousarray(widths, dtype=np.uint32)
+        a = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        tickets = np.zeros(o.size, dtype=np.uint64)
+        ptr = lambda x: ctypes.c_void_p(x.ctypes.data)
+        _check(lib().hth_serve_replay(self._h, ptr(base), ptr(o), ptr(n), ptr(w), ptr(a), o.size, ptr(tickets)))
+        return tickets
+
+    def pause(self, paused=True):
+        """Hold (or release) batching; submitted requests queue meanwhile."""
+        _check(lib().hth_serve_pause(self._h, 1 if paused else 0))
+
+    def stats(self):
+        r = ServeReport()
+        _check(lib().hth_serve_stats(self._h, ctypes.byref(r)))
+        return r.as_dict()
+
+    def reset_stats(self):
+        _check(lib().hth_serve_reset_stats(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            h, self._h = self._h, None
+            _check(lib().hth_serve_destroy(h))
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

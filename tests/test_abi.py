@@ -75,3 +75,28 @@ def test_gpu_path_does_not_touch_the_oracle():
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert not re.search(r'^\s*(import|from)\s+paper_2104_08865_amd|^\s*#\s*include\s*[<"][^>"]*(hth_family|hth_kernels|hth\.h)',
                                  text, re.M), f
+
+
+def test_serve_config_rejections(lib):
+    """hth_serve_create validates its limits before any device allocation."""
+    from paper_2104_08865_amd import hth
+    h = ctypes.c_void_p()
+    seed = ctypes.c_void_p(1)  # never dereferenced: every case fails first
+    assert lib.hth_serve_create(None, seed, ctypes.byref(h)) == hth.HTH_E_INVALID
+    assert lib.hth_serve_create(ctypes.byref(hth.ServeConfig()), seed, None) == hth.HTH_E_INVALID
+    cases = [
+        (dict(max_device_bytes=1 << 20, max_request_bytes=2 << 20), b"max_request_bytes"),
+        (dict(host_stage_bytes=1 << 20), b"max_request_bytes"),  # default 16 MiB requests
+        (dict(slots=9), b"slots"),
+        (dict(max_batch_bytes=(1 << 36) + 1), b"max_batch_bytes"),
+        (dict(max_batch_requests=(1 << 22) + 1), b"max_batch_requests"),
+        (dict(max_outstanding=(1 << 24) + 1), b"max_outstanding"),
+    ]
+    for cfg, word in cases:
+        rc = lib.hth_serve_create(ctypes.byref(hth.ServeConfig(**cfg)), seed, ctypes.byref(h))
+        assert rc == hth.HTH_E_INVALID and word in lib.hth_last_error(), cfg
+    rc = lib.hth_serve_create(ctypes.byref(hth.ServeConfig()), None, ctypes.byref(h))
+    assert rc == hth.HTH_E_INVALID and b"seed" in lib.hth_last_error()
+    t = ctypes.c_uint64()
+    assert lib.hth_serve_submit(None, None, 0, 16, ctypes.byref(t)) == hth.HTH_E_INVALID
+    assert lib.hth_serve_destroy(None) == hth.HTH_OK
