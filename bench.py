@@ -235,6 +235,7 @@ def run_throughput(args):
 
 
 SERVE_LOADS = (0.25, 0.5, 0.8)
+SERVE_CLIENTS = 4  # replay threads submitting (copies into the staging overlap)
 
 
 def serve_legs(n_req, verify=False):
@@ -257,10 +258,11 @@ def serve_legs(n_req, verify=False):
     torch.cuda.synchronize()
     res = {"workload": "serving: lognormal lengths (median 4 KiB, sigma 2, cap 16 MiB), widths 16/40 50/50, "
                        "bytes splitmix64 seed 5, submitted from host memory; Poisson arrivals",
-           "requests_per_load": n_req, "mean_request_bytes": total / n_req, "loads": []}
+           "requests_per_load": n_req, "mean_request_bytes": total / n_req, "client_threads": SERVE_CLIENTS,
+           "loads": []}
     with hth.Server(seed, max_device_bytes=2 << 30, host_stage_bytes=2 << 30) as srv:
         # capacity: every request due at once
-        tickets = srv.replay(data, offs, lens, widths, np.zeros(n_req, dtype=np.uint64))
+        tickets = srv.replay(data, offs, lens, widths, np.zeros(n_req, dtype=np.uint64), threads=SERVE_CLIENTS)
         got = srv.wait_many(tickets)
         st = srv.stats()
         cap_rps = st["completed"] / st["elapsed_s"]
@@ -271,7 +273,7 @@ def serve_legs(n_req, verify=False):
             rate = load * cap_rps
             arrive = (np.cumsum(unit_gaps) / rate * 1e9).astype(np.uint64)
             srv.reset_stats()
-            tickets = srv.replay(data, offs, lens, widths, arrive)
+            tickets = srv.replay(data, offs, lens, widths, arrive, threads=SERVE_CLIENTS)
             out = srv.wait_many(tickets)
             st = srv.stats()
             same = bool((out == got).all())

@@ -246,12 +246,15 @@ hth_status hth_serve_wait_many(hth_server *server, const uint64_t *tickets, uint
                                uint32_t out_stride);
 
 /* Load replay: submits request i (bytes base + offsets[i], lengths[i],
-   width widths[i]) at arrival_ns[i] nanoseconds after the call starts
-   (non-decreasing), retrying while the server answers HTH_E_BUSY; tickets
-   go to tickets[i].  Returns after the last submit, not after completion. */
+   width widths[i]) at arrival_ns[i] nanoseconds after the call starts,
+   retrying while the server answers HTH_E_BUSY; tickets go to tickets[i].
+   `threads` client threads (1..64) share the requests round robin (request
+   i goes to thread i mod threads, each in arrival order), so copies into the
+   staging overlap.  Returns after the last submit, not after completion;
+   on an error other than BUSY the remaining requests are not submitted. */
 hth_status hth_serve_replay(hth_server *server, const uint8_t *base, const uint64_t *offsets,
                             const uint64_t *lengths, const uint32_t *widths, const uint64_t *arrival_ns,
-                            uint64_t n, uint64_t *tickets);
+                            uint64_t n, uint32_t threads, uint64_t *tickets);
 
 /* Hold (paused != 0) or release (0) batching: while held, submitted
    requests queue up (within the staging and outstanding limits) and no new

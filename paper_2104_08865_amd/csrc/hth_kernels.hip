@@ -239,14 +239,14 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
   return before + x - v;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
-                                                                  uint64_t count, uint32_t exec_bytes,
-                                                                  uint64_t* __restrict__ block_sums,
-                                                                  uint32_t* __restrict__ ctl) {
+// Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
+// accumulators and work of its kPlanBlock strings.
+__device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
+                                uint32_t exec_bytes, uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
   // the fill kernel appends bucket leaders to this counter
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
-  const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + threadIdx.x * kPlanPer;
+  if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
+  const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t L[kPlanPer];
   for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
   for (int j = 0; j < kPlanCandidates; ++j) {
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
     a = block_sum(a, lds);
     w = block_sum(w, lds);
     if (threadIdx.x == 0) {
-      uint64_t* bs = block_sums + ((uint64_t)blockIdx.x * kPlanCandidates + j) * kPlanSums;
+      uint64_t* bs = block_sums + ((uint64_t)blk * kPlanCandidates + j) * kPlanSums;
       bs[0] = t;
       bs[1] = a;
       bs[2] = w;
@@ -271,8 +271,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
   }
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
-    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
+// Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
+__device__ void plan_fill_body(
+    uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
   const uint64_t total_work = jsel >= 0 ? tw[jsel] : 0;
   uint64_t bucket = (total_work + kMaxBuckets - 1) / kMaxBuckets;
   if (bucket < kMinBucketBytes) bucket = kMinBucketBytes;
-  if (blockIdx.x == 0 && tid == 0) {
+  if (blk == 0 && tid == 0) {
     ctl[kCtlNext] = 0;
     ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
     ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
   if (jsel < 0) return;  // uniform over the grid
   // Tasks, accumulators and work of the blocks before this one.
   uint64_t pt = 0, pa = 0, pw = 0;
-  for (uint32_t b = tid; b < blockIdx.x; b += kPlanThreads) {
+  for (uint32_t b = tid; b < blk; b += kPlanThreads) {
     const uint64_t* bs = block_sums + ((uint64_t)b * kPlanCandidates + jsel) * kPlanSums;
     pt += bs[0];
     pa += bs[1];
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
   const uint64_t acc_base = block_sum(pa, lds);
   const uint64_t work_base = block_sum(pw, lds);
 
-  const uint64_t base = (uint64_t)blockIdx.x * kPlanBlock + tid * kPlanPer;
+  const uint64_t base = (uint64_t)blk * kPlanBlock + tid * kPlanPer;
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
   uint64_t st = 0, sa = 0, sw = 0;
   for (int i = 0; i < kPlanPer; ++i) {
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
   // after a boundary, so no bucket is empty.  Leaders carry bit 31 in the
   // table and are appended to bucket_lead (in no particular order) with one
   // atomic per workgroup.
-  const uint64_t first = (uint64_t)blockIdx.x * kPlanBlock;
+  const uint64_t first = (uint64_t)blk * kPlanBlock;
   const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
   const uint64_t texec = 128ull << (3 * jsel);
   const uint64_t unit = texec * exec_bytes + kTaskOverheadBytes;  // work of a full task
@@ -410,6 +411,38 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t task = task_base + e;
     if (task_string[task] >> 31) bucket_lead[at++] = (uint32_t)task;
   }
+}
+
+
+__global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
+                                                                  uint64_t count, uint32_t exec_bytes,
+                                                                  uint64_t* __restrict__ block_sums,
+                                                                  uint32_t* __restrict__ ctl) {
+  plan_count_body(blockIdx.x, lengths, count, exec_bytes, block_sums, ctl);
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
+    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
+    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
+    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
+    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
+    uint32_t* __restrict__ ctl) {
+  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, block_sums, nblocks, cap_tasks, cap_accs, min_j, max_j,
+                 target_tasks, task_string, task_start, acc_start, bucket_lead, ctl);
+}
+
+// Both steps in one workgroup, for batches of at most kPlanBlock strings
+// (one launch instead of two).  The barrier between the steps also makes
+// step 1's global writes visible to the whole workgroup.
+__global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
+    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint64_t* __restrict__ block_sums,
+    uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j, uint64_t target_tasks,
+    uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
+    uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ ctl) {
+  plan_count_body(0, lengths, count, exec_bytes, block_sums, ctl);
+  __syncthreads();
+  plan_fill_body(0, lengths, count, exec_bytes, block_sums, 1, cap_tasks, cap_accs, min_j, max_j, target_tasks,
+                 task_string, task_start, acc_start, bucket_lead, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,6 +565,105 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
   }
 }
 
+// The last pass of a string, nv < 128 executions starting at execution p:
+// execution p + 16e + q goes to lane group q (e = 0 .. ceil(nv/16) - 1), so
+// the executions spread over all 16 lane groups (a lane does at most
+// ceil(nv/16) of them instead of up to 8).  Execution 16e + q is child
+// q mod 8 of level-1 node 2e + q/8; the 8 children of a node sit in the
+// lane groups of one half-row and are summed across lanes.  Complete level-1
+// nodes either join level-2 node p/64 (when nv >= 64 and node < 8) or are
+// leftover items of level 1; the executions of the incomplete level-1 node
+// are leftover items of level 0.  Called by the whole wave (nv uniform).
+template <int WIDTH>
+__device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
+                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][kBlock]) {
+  using Ly = Layout<WIDTH>;
+  constexpr int K = Family<WIDTH>::K;
+  constexpr uint64_t XB = Ly::exec_bytes;
+  const int lane = threadIdx.x;
+  const int q = lane >> 2, r = lane & 3;
+  const int h = q >> 3, pos0 = q & 7;
+  const uint32_t full1 = nv / 8;  // complete level-1 nodes of the pass
+  const bool full2 = nv >= 64;    // level-2 node p/64 complete
+  uint64_t k0[K];                 // level-0 key of this lane's child position
+#pragma unroll
+  for (int t = 0; t < K; ++t) k0[t] = pos0 < kFan - 1 ? c.ent[Ly::tree + (t * kLevels) * (kFan - 1) + pos0] : 0;
+  uint64_t s0[K], s1[K];  // terms of level-2 node p/64 (lanes of pos0 == 0)
+#pragma unroll
+  for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
+  const uint32_t steps = (nv + 15) / 16;
+  for (uint32_t e = 0; e < steps; ++e) {
+    const uint32_t i = 16 * e + (uint32_t)q;  // execution within the pass
+    const uint32_t m = 2 * e + (uint32_t)h;   // its level-1 node
+    const bool node_full = m < full1;
+    uint64_t t0[K], t1[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) t0[t] = t1[t] = 0;
+    if (i < nv) {
+      uint64_t z0[K], z1[K];
+      ehc2<WIDTH>(str + (p + i) * XB + 16 * r, uniform_keys(c.ent + Ly::ehc), z0, z1);
+      if (node_full) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          t0[t] = pos0 < kFan - 1 ? nh_acc(0, z0[t], k0[t]) : z0[t];
+          t1[t] = pos0 < kFan - 1 ? nh_acc(0, z1[t], k0[t]) : z1[t];
+        }
+      } else {
+        // child of the incomplete level-1 node: leftover item (0, pos0)
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + pos0) * kBlock;
+          F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
+          F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
+        }
+      }
+    }
+    // sum the 8 children of each level-1 node (lane bits 2..4 = q mod 8)
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      t0[t] += shfl_xor64(t0[t], 4);
+      t1[t] += shfl_xor64(t1[t], 4);
+      t0[t] += shfl_xor64(t0[t], 8);
+      t1[t] += shfl_xor64(t1[t], 8);
+      t0[t] += shfl_xor64(t0[t], 16);
+      t1[t] += shfl_xor64(t1[t], 16);
+    }
+    if (pos0 == 0 && node_full) {
+      if (full2 && m < (uint32_t)kFan) {
+        // child m of level-2 node p/64
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          if (m < (uint32_t)kFan - 1) {
+            const uint64_t key = c.ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + m];
+            s0[t] = nh_acc(s0[t], t0[t], key);
+            s1[t] = nh_acc(s1[t], t1[t], key);
+          } else {
+            s0[t] += t0[t];
+            s1[t] += t1[t];
+          }
+        }
+      } else {
+        // complete level-1 node with an incomplete parent: leftover (1, m mod 8)
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + (m & 7)) * kBlock;
+          F[t] = nh_acc(F[t], t0[t], kf[2 * r]);
+          F[t] = nh_acc(F[t], t1[t], kf[2 * r + 1]);
+        }
+      }
+    }
+  }
+  if (full2) {
+    // even children sit in lanes 0..3, odd ones in lanes 32..35
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      s0[t] += shfl64(s0[t], (lane & 3) + 32);
+      s1[t] += shfl64(s1[t], (lane & 3) + 32);
+    }
+    fold_up<WIDTH>(c, 2, p >> 6, s0, s1, F, lacc);
+  }
+}
+
 template <int WIDTH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void hash_main_kernel(MainArgs a) {
   using Fm = Family<WIDTH>;
@@ -588,70 +720,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint64_t g0 = tau * texec;
     const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
     for (uint64_t p = g0; p < g1; p += 128) {
-      const uint64_t nv = N - p < 128 ? N - p : 128;
-      const int64_t cnt64 = (int64_t)nv - 8 * q;
-      const int cnt = cnt64 < 0 ? 0 : (cnt64 > 8 ? 8 : (int)cnt64);
+      if (N - p < 128) {
+        // the string's last, partial pass
+        partial_pass<WIDTH>(c, str, p, (uint32_t)(N - p), F, lacc);
+        break;
+      }
+      // full pass: lane group q takes the 8 consecutive executions
+      // p + 8q .. p + 8q + 7, i.e. all children of level-1 node p/8 + q
       uint64_t a0[K], a1[K];
 #pragma unroll
       for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
       const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
       for (int e = 0; e < 8; ++e) {
-        if (e < cnt) {
-          uint64_t z0[K], z1[K];
-          ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
-          if (cnt == 8) {
-            // level 0 of every tree: child e of this lane's level-1 node
-            if (e < kFan - 1) {
+        uint64_t z0[K], z1[K];
+        ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
+        // level 0 of every tree: child e of this lane's level-1 node
+        if (e < kFan - 1) {
 #pragma unroll
-              for (int t = 0; t < K; ++t) {
-                const uint64_t key = uniform_keys(ent)[Ly::tree + (t * kLevels) * (kFan - 1) + e];
-                a0[t] = nh_acc(a0[t], z0[t], key);
-                a1[t] = nh_acc(a1[t], z1[t], key);
-              }
-            } else {
+          for (int t = 0; t < K; ++t) {
+            const uint64_t key = uniform_keys(ent)[Ly::tree + (t * kLevels) * (kFan - 1) + e];
+            a0[t] = nh_acc(a0[t], z0[t], key);
+            a1[t] = nh_acc(a1[t], z1[t], key);
+          }
+        } else {
 #pragma unroll
-              for (int t = 0; t < K; ++t) {
-                a0[t] += z0[t];
-                a1[t] += z1[t];
-              }
-            }
-          } else {
-            // incomplete level-1 node: these leaves are level-0 leftovers
-#pragma unroll
-            for (int t = 0; t < K; ++t) {
-              const uint64_t* kf = ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + e) * kBlock;
-              F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
-              F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
-            }
+          for (int t = 0; t < K; ++t) {
+            a0[t] += z0[t];
+            a1[t] += z1[t];
           }
         }
       }
-      // level 1 -> level 2: this lane holds level-1 node 8 * (p/64) + q
-      // (for every tree and its two instances) when its column is complete.
-      const bool half_full = (q < 8) ? nv >= 64 : nv >= 128;
+      // level 1 -> level 2: lane group q holds level-1 node p/8 + q, child
+      // pos1 of level-2 node p/64 + q/8
       const int pos1 = q & 7;
-      if (cnt == 8 && !half_full) {
-        // complete level-1 node in an incomplete level-2 group: leftover (1, pos1)
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + pos1) * kBlock;
-          F[t] = nh_acc(F[t], a0[t], kf[2 * r]);
-          F[t] = nh_acc(F[t], a1[t], kf[2 * r + 1]);
-        }
-      }
       uint64_t n0[K], n1[K];
 #pragma unroll
       for (int t = 0; t < K; ++t) {
-        uint64_t t0 = 0, t1 = 0;
-        if (half_full) {
-          if (pos1 < kFan - 1) {
-            const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
-            t0 = nh_acc(0, a0[t], key);
-            t1 = nh_acc(0, a1[t], key);
-          } else {
-            t0 = a0[t];
-            t1 = a1[t];
-          }
+        uint64_t t0, t1;
+        if (pos1 < kFan - 1) {
+          const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
+          t0 = nh_acc(0, a0[t], key);
+          t1 = nh_acc(0, a1[t], key);
+        } else {
+          t0 = a0[t];
+          t1 = a1[t];
         }
         t0 += shfl_xor64(t0, 4);
         t1 += shfl_xor64(t1, 4);
@@ -671,8 +783,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         b0[t] = shfl64(n0[t], (lane & 3) + 32);
         b1[t] = shfl64(n1[t], (lane & 3) + 32);
       }
-      if (nv >= 64) fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
-      if (nv >= 128) fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
+      fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
+      fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
     }
 
     if (tau == ntask - 1) {
@@ -773,6 +885,12 @@ uint64_t entropy_words_total() { return kEntropyWords; }
 
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const uint32_t nblocks = (uint32_t)((p.count + kPlanBlock - 1) / kPlanBlock);
+  if (nblocks == 1) {
+    hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
+                       p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
+                       p.task_start, p.acc_start, p.bucket_lead, p.ctl);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
                      p.exec_bytes, p.block_sums, p.ctl);
   hipError_t e = hipGetLastError();

@@ -23,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -113,14 +114,17 @@ struct hth_server {
   uint8_t* d_ring = nullptr;
   std::vector<Slot> slots;
 
-  // submitters: one at a time (FIFO order of the host ring = queue order)
-  std::mutex submit_mu;
-  // host ring and pending queue
+  // host ring and pending queue (queue order = host ring order); a
+  // request's bytes are copied outside the lock, so the worker admits a
+  // request only once its `copied` flag is set
   std::mutex q_mu;
   std::condition_variable q_cv;
   Ring host;
   std::deque<Request> pending;
   uint64_t next_ticket = 1;
+  std::unique_ptr<std::atomic<uint8_t>[]> copied;  // per ticket slot
+  std::atomic<uint64_t> ready_hint{0};            // submits since the worker last looked
+  std::atomic<bool> worker_idle{false};
 
   Ring dev;  // worker only
   uint32_t next_slot = 0;
@@ -171,6 +175,7 @@ bool launch_batch(hth_server* s, uint32_t si) {
     std::lock_guard<std::mutex> lk(s->q_mu);
     while (!s->pending.empty() && sl.reqs.size() < s->cfg.max_batch_requests) {
       Request& r = s->pending.front();
+      if (!s->copied[r.ticket & s->mask].load(std::memory_order_acquire)) break;  // bytes still being copied
       if (!sl.reqs.empty() && bytes + r.len > s->cfg.max_batch_bytes) break;
       uint64_t pos = 0;
       if (!s->dev.alloc(pad(r.len), &pos)) {
@@ -305,22 +310,30 @@ void worker_main(hth_server* s) {
     while (retire_one(s)) progress = true;
     if (s->failed.load()) break;
     Slot& next = s->slots[s->next_slot];
-    if (!next.busy && !s->paused.load()) {
-      bool have = false;
-      {
-        std::lock_guard<std::mutex> lk(s->q_mu);
-        have = !s->pending.empty();
-      }
-      if (have && launch_batch(s, s->next_slot)) {
+    if (!next.busy && !s->paused.load() && s->ready_hint.load(std::memory_order_acquire)) {
+      s->ready_hint.store(0, std::memory_order_relaxed);  // launch_batch looks at the whole queue
+      if (launch_batch(s, s->next_slot)) {
         s->next_slot = (s->next_slot + 1) % (uint32_t)s->slots.size();
         progress = true;
+      }
+      bool more = false;
+      {
+        std::lock_guard<std::mutex> lk(s->q_mu);
+        more = !s->pending.empty();
+      }
+      if (more) {
+        s->ready_hint.fetch_add(1, std::memory_order_relaxed);  // look again next round
+        if (!progress) std::this_thread::yield();  // the head request's bytes are still being copied
       }
     }
     if (progress) continue;
     if (s->inflight.empty()) {
       std::unique_lock<std::mutex> lk(s->q_mu);
-      s->q_cv.wait_for(lk, std::chrono::milliseconds(50),
-                       [&] { return s->stop.load() || (!s->pending.empty() && !s->paused.load()); });
+      s->worker_idle.store(true);
+      s->q_cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
+        return s->stop.load() || (s->ready_hint.load() && !s->paused.load());
+      });
+      s->worker_idle.store(false);
     } else {
       std::this_thread::yield();  // a batch is in flight: poll its event
     }
@@ -412,6 +425,8 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
   try {
     s->entries.resize(outstanding);
     s->slots.resize(c.slots);
+    s->copied.reset(new std::atomic<uint8_t>[outstanding]);
+    for (uint32_t i = 0; i < outstanding; ++i) s->copied[i].store(0);
   } catch (...) {
     delete s;
     return fail(HTH_E_OOM, "hth_serve_create: host allocation");
@@ -466,7 +481,6 @@ hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len,
     return fail(HTH_E_TOO_LARGE, "hth_serve_submit: %llu bytes above the limit %llu", (unsigned long long)len,
                 (unsigned long long)s->cfg.max_request_bytes);
   if (s->failed.load()) return server_error(s);
-  std::lock_guard<std::mutex> sub(s->submit_mu);
   uint64_t t = 0, pos = 0;
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
@@ -496,13 +510,16 @@ hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len,
       return HTH_E_BUSY;
     }
     ++s->next_ticket;
-  }
-  if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
-  {
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->copied[t & s->mask].store(0, std::memory_order_relaxed);
     s->pending.push_back(Request{t, pos, 0, len, out_width, false, t0});
   }
-  s->q_cv.notify_all();
+  if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
+  s->copied[t & s->mask].store(1, std::memory_order_release);
+  s->ready_hint.fetch_add(1);  // sequentially consistent with the worker's idle flag
+  if (s->worker_idle.load()) {
+    std::lock_guard<std::mutex> lk(s->q_mu);  // pairs with the worker's predicate check
+    s->q_cv.notify_all();
+  }
   *ticket = t;
   return HTH_OK;
 }
@@ -529,21 +546,46 @@ hth_status hth_serve_wait_many(hth_server* s, const uint64_t* tickets, uint64_t 
 }
 
 hth_status hth_serve_replay(hth_server* s, const uint8_t* base, const uint64_t* offsets, const uint64_t* lengths,
-                            const uint32_t* widths, const uint64_t* arrival_ns, uint64_t n, uint64_t* tickets) {
+                            const uint32_t* widths, const uint64_t* arrival_ns, uint64_t n, uint32_t threads,
+                            uint64_t* tickets) {
   if (!s || (n && (!base || !offsets || !lengths || !widths || !arrival_ns || !tickets)))
     return fail(HTH_E_INVALID, "hth_serve_replay: null pointer");
+  if (threads == 0 || threads > 64) return fail(HTH_E_INVALID, "hth_serve_replay: threads %u not in 1..64", threads);
   const Clock::time_point t0 = Clock::now();
-  for (uint64_t i = 0; i < n; ++i) {
-    const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
-    while (Clock::now() < due) {
+  std::atomic<int> first_err{HTH_OK};
+  std::string err_msg;
+  std::mutex err_mu;
+  // client k submits requests k, k + threads, ... at their arrival times
+  auto client = [&](uint32_t k) {
+    for (uint64_t i = k; i < n && first_err.load() == HTH_OK; i += threads) {
+      const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
+      while (Clock::now() < due) {
+      }
+      for (;;) {
+        hth_status st = hth_serve_submit(s, base + offsets[i], lengths[i], widths[i], tickets + i);
+        if (st == HTH_OK) break;
+        if (st != HTH_E_BUSY) {
+          std::lock_guard<std::mutex> lk(err_mu);
+          if (first_err.load() == HTH_OK) {
+            err_msg = hth_last_error();
+            first_err.store(st);
+          }
+          return;
+        }
+        std::this_thread::yield();  // staging full: wait for a batch to retire
+      }
     }
-    for (;;) {
-      hth_status st = hth_serve_submit(s, base + offsets[i], lengths[i], widths[i], tickets + i);
-      if (st == HTH_OK) break;
-      if (st != HTH_E_BUSY) return st;
-      std::this_thread::yield();  // staging full: wait for a batch to retire
-    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (uint32_t k = 1; k < threads; ++k) pool.emplace_back(client, k);
+  } catch (...) {
+    first_err.store(HTH_E_OOM);
+    err_msg = "replay thread";
   }
+  client(0);
+  for (auto& th : pool) th.join();
+  if (first_err.load() != HTH_OK) return fail(first_err.load(), "hth_serve_replay: %s", err_msg.c_str());
   return HTH_OK;
 }
 
@@ -552,6 +594,7 @@ hth_status hth_serve_pause(hth_server* s, int32_t paused) {
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
     s->paused.store(paused != 0);
+    if (!paused) s->ready_hint.fetch_add(1);
   }
   s->q_cv.notify_all();
   return HTH_OK;

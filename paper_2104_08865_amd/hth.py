@@ -91,7 +91,7 @@ def lib():
         L.hth_serve_poll.argtypes = [vp, u64, vp]
         L.hth_serve_wait.argtypes = [vp, u64, vp]
         L.hth_serve_wait_many.argtypes = [vp, vp, u64, vp, u32]
-        L.hth_serve_replay.argtypes = [vp, vp, vp, vp, vp, vp, u64, vp]
+        L.hth_serve_replay.argtypes = [vp, vp, vp, vp, vp, vp, u64, u32, vp]
         L.hth_serve_stats.argtypes = [vp, ctypes.POINTER(ServeReport)]
         L.hth_serve_reset_stats.argtypes = [vp]
         L.hth_serve_destroy.argtypes = [vp]
@@ -322,9 +322,10 @@ class Server:
                                          ctypes.c_void_p(out.ctypes.data), 40))
         return out
 
-    def replay(self, base, offsets, lengths, widths, arrival_ns):
+    def replay(self, base, offsets, lengths, widths, arrival_ns, threads=1):
         """Submit request i (base[offsets[i]:][:lengths[i]], widths[i]) at
-        arrival_ns[i] after the call starts; returns the tickets."""
+        arrival_ns[i] after the call starts, from `threads` client threads;
+        returns the tickets."""
         base = np.ascontiguousarray(base, dtype=np.uint8)
         o = np.ascontiguousarray(offsets, dtype=np.uint64)
         n = np.ascontiguousarray(lengths, dtype=np.uint64)
@@ -332,7 +333,8 @@ class Server:
         a = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
         tickets = np.zeros(o.size, dtype=np.uint64)
         ptr = lambda x: ctypes.c_void_p(x.ctypes.data)
-        _check(lib().hth_serve_replay(self._h, ptr(base), ptr(o), ptr(n), ptr(w), ptr(a), o.size, ptr(tickets)))
+        _check(lib().hth_serve_replay(self._h, ptr(base), ptr(o), ptr(n), ptr(w), ptr(a), o.size, threads,
+                                      ptr(tickets)))
         return tickets
 
     def pause(self, paused=True):

@@ -121,20 +121,28 @@ def test_limits_too_large_and_busy(env):
     assert [first] + rest == [bytes(r) for r in ref]
 
 
-def test_replay_poisson_and_spot_check(env):
-    """A Poisson replay (cfg of the serving workload, 20,000 requests at
-    20,000 requests/s): every result equals hth_hash_batch's, 2% of them are
-    checked against the oracle, and the report carries latencies."""
-    torch, hth = env["torch"], env["hth"]
+@pytest.fixture(scope="module")
+def requests20k():
     n = 20_000
     lens = wl.lognormal_lengths(seed=5, n=n)
     widths = wl.coin_widths(5, n)
-    arrive = np.cumsum(wl.poisson_gaps(5, n, 20_000.0))
     offs, total = wl.pack(lens)
-    print(f"[serve] replay requests={n} bytes={total}", flush=True)
-    data = wl.random_bytes(5, total)
+    return {"n": n, "lens": lens, "widths": widths, "offs": offs, "total": total, "data": wl.random_bytes(5, total),
+            "arrive": np.cumsum(wl.poisson_gaps(5, n, 20_000.0))}
+
+
+@pytest.mark.parametrize("threads", [1, 4])
+def test_replay_poisson_and_spot_check(env, requests20k, threads):
+    """A Poisson replay of the serving workload (20,000 requests at 20,000
+    requests/s, from 1 and from 4 client threads): every result equals
+    hth_hash_batch's, 2% of them are checked against the oracle, and the
+    report carries latencies."""
+    torch, hth = env["torch"], env["hth"]
+    rq = requests20k
+    n, lens, widths, offs, data = rq["n"], rq["lens"], rq["widths"], rq["offs"], rq["data"]
+    print(f"[serve] replay requests={n} bytes={rq['total']} threads={threads}", flush=True)
     with hth.Server(env["seed"]) as srv:
-        tickets = srv.replay(data, offs, lens, widths, (arrive * 1e9).astype(np.uint64))
+        tickets = srv.replay(data, offs, lens, widths, (rq["arrive"] * 1e9).astype(np.uint64), threads=threads)
         got = srv.wait_many(tickets)
         st = srv.stats()
     assert st["completed"] == n and st["latency_p99_us"] >= st["latency_p50_us"] > 0
@@ -145,5 +153,26 @@ def test_replay_poisson_and_spot_check(env):
         sel = np.nonzero(widths == w)[0]
         ref = hth.hash_batch(env["seed"], d, o[torch.from_numpy(sel).cuda()], ln[torch.from_numpy(sel).cuda()], w)
         assert (got[sel, :w] == ref.cpu().numpy()).all()
-    spot = np.arange(0, n, 50)
+    spot = np.arange(threads, n, 50)
     assert (got[spot] == _oracle(env, data, offs[spot], lens[spot], widths[spot])).all()
+
+
+def test_burst_from_many_threads(env, requests20k):
+    """Every request due at once from 8 client threads with a small staging
+    area (submits are refused BUSY and retried): all results still match."""
+    torch, hth = env["torch"], env["hth"]
+    rq = requests20k
+    n = 5000
+    lens, widths, offs, data = rq["lens"][:n], rq["widths"][:n], rq["offs"][:n], rq["data"]
+    with hth.Server(env["seed"], host_stage_bytes=32 << 20, max_device_bytes=32 << 20) as srv:
+        tickets = srv.replay(data, offs, lens, widths, np.zeros(n, dtype=np.uint64), threads=8)
+        got = srv.wait_many(tickets)
+        st = srv.stats()
+    assert st["completed"] == n
+    d = torch.from_numpy(data).cuda()
+    o = torch.from_numpy(offs.view(np.int64)).cuda()
+    ln = torch.from_numpy(lens.view(np.int64)).cuda()
+    for w in (16, 40):
+        sel = np.nonzero(widths == w)[0]
+        ref = hth.hash_batch(env["seed"], d, o[torch.from_numpy(sel).cuda()], ln[torch.from_numpy(sel).cuda()], w)
+        assert (got[sel, :w] == ref.cpu().numpy()).all()
