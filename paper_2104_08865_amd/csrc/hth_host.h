@@ -51,9 +51,15 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 
 // Enqueues the planner and the hashing kernel of one batch on `stream`
 // using workspace `w` (events optional, recorded around the hashing kernel).
+// max_waves, when nonzero, caps the hashing kernel's grid: a caller that
+// knows the lengths on the host passes an upper bound of the batch's tasks.
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
-                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop);
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0);
+
+// Upper bound of the tasks a string of `len` bytes can make (at the finest
+// task size), for max_waves.
+uint64_t task_bound(uint64_t len, uint32_t out_width);
 
 }  // namespace host
 }  // namespace hth

@@ -203,17 +203,26 @@ constexpr int kPlanBlock = kPlanThreads * kPlanPer;
 
 constexpr int kPlanWaves = kPlanThreads / 64;
 
-// Sum of v over the block, returned to every thread.
-__device__ uint64_t block_sum(uint64_t v, uint64_t* lds) {
+// Sums of n values over the block, returned to every thread, with one pair
+// of barriers for all of them.
+template <int NV>
+__device__ void block_sum_n(uint64_t (&v)[NV], uint64_t (*lds)[NV]) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint64_t t = 0;
+  for (int k = 0; k < NV; ++k)
 #pragma unroll
-  for (int i = 0; i < kPlanWaves; ++i) t += lds[i];
-  return t;
+    for (int m = 32; m >= 1; m >>= 1) v[k] += shfl_xor64(v[k], m);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kPlanWaves; ++i) t += lds[i][k];
+    v[k] = t;
+  }
 }
 
 // Exclusive prefix sum of v over the block (thread order); `total` receives
@@ -243,12 +252,13 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
 // accumulators and work of its kPlanBlock strings.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
                                 uint32_t exec_bytes, uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t lds[kPlanWaves];
+  __shared__ uint64_t lds[kPlanWaves][kPlanCandidates * kPlanSums];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t L[kPlanPer];
   for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
+  uint64_t v[kPlanCandidates * kPlanSums];
   for (int j = 0; j < kPlanCandidates; ++j) {
     uint64_t t = 0, a = 0, w = 0;
     for (int i = 0; i < kPlanPer; ++i) {
@@ -259,15 +269,16 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
       a += ai;
       w += L[i] + kTaskOverheadBytes * ti;
     }
-    t = block_sum(t, lds);
-    a = block_sum(a, lds);
-    w = block_sum(w, lds);
-    if (threadIdx.x == 0) {
-      uint64_t* bs = block_sums + ((uint64_t)blk * kPlanCandidates + j) * kPlanSums;
-      bs[0] = t;
-      bs[1] = a;
-      bs[2] = w;
-    }
+    v[j * kPlanSums + 0] = t;
+    v[j * kPlanSums + 1] = a;
+    v[j * kPlanSums + 2] = w;
+  }
+  block_sum_n(v, lds);
+  if (threadIdx.x < kPlanCandidates * kPlanSums) {
+    uint64_t x = v[0];
+    for (int k = 1; k < kPlanCandidates * kPlanSums; ++k)
+      if ((int)threadIdx.x == k) x = v[k];
+    block_sums[(uint64_t)blk * kPlanCandidates * kPlanSums + threadIdx.x] = x;
   }
 }
 
@@ -279,22 +290,22 @@ __device__ void plan_fill_body(
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
+  __shared__ uint64_t ldsn[kPlanWaves][kPlanCandidates * kPlanSums];
+  __shared__ uint64_t lds3[kPlanWaves][kPlanSums];
   __shared__ uint32_t incl[kPlanBlock];
   __shared__ uint64_t wstart[kPlanBlock];
   const int tid = threadIdx.x;
   // Totals of every candidate over all blocks (threads stride over blocks).
+  uint64_t tot[kPlanCandidates * kPlanSums];
+  for (int k = 0; k < kPlanCandidates * kPlanSums; ++k) tot[k] = 0;
+  for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
+    for (int k = 0; k < kPlanCandidates * kPlanSums; ++k) tot[k] += block_sums[(uint64_t)b * kPlanCandidates * kPlanSums + k];
+  block_sum_n(tot, ldsn);
   uint64_t tt[kPlanCandidates], ta[kPlanCandidates], tw[kPlanCandidates];
   for (int j = 0; j < kPlanCandidates; ++j) {
-    uint64_t t = 0, a = 0, w = 0;
-    for (uint32_t b = tid; b < nblocks; b += kPlanThreads) {
-      const uint64_t* bs = block_sums + ((uint64_t)b * kPlanCandidates + j) * kPlanSums;
-      t += bs[0];
-      a += bs[1];
-      w += bs[2];
-    }
-    tt[j] = block_sum(t, lds);
-    ta[j] = block_sum(a, lds);
-    tw[j] = block_sum(w, lds);
+    tt[j] = tot[j * kPlanSums + 0];
+    ta[j] = tot[j * kPlanSums + 1];
+    tw[j] = tot[j * kPlanSums + 2];
   }
   // Task size: the coarsest level in [min_j, max_j] that still yields
   // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
@@ -317,16 +328,13 @@ __device__ void plan_fill_body(
   }
   if (jsel < 0) return;  // uniform over the grid
   // Tasks, accumulators and work of the blocks before this one.
-  uint64_t pt = 0, pa = 0, pw = 0;
-  for (uint32_t b = tid; b < blk; b += kPlanThreads) {
-    const uint64_t* bs = block_sums + ((uint64_t)b * kPlanCandidates + jsel) * kPlanSums;
-    pt += bs[0];
-    pa += bs[1];
-    pw += bs[2];
-  }
-  const uint64_t task_base = block_sum(pt, lds);
-  const uint64_t acc_base = block_sum(pa, lds);
-  const uint64_t work_base = block_sum(pw, lds);
+  uint64_t pre[kPlanSums] = {0, 0, 0};
+  for (uint32_t b = tid; b < blk; b += kPlanThreads)
+    for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[((uint64_t)b * kPlanCandidates + jsel) * kPlanSums + k];
+  block_sum_n(pre, lds3);
+  const uint64_t task_base = pre[0];
+  const uint64_t acc_base = pre[1];
+  const uint64_t work_base = pre[2];
 
   const uint64_t base = (uint64_t)blk * kPlanBlock + tid * kPlanPer;
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
@@ -691,10 +699,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   // leaves once the counter ran past the last bucket.
   const uint32_t ntasks_all = uniform(a.ctl[kCtlTotal]);
   uint32_t task = 0;
-  bool fetch = true;
+  bool fetch = true, first = true;
   for (;;) {
     __builtin_amdgcn_wave_barrier();
     if (fetch) {
+      if (first) {
+        // a batch with fewer buckets than waves: most waves leave on a
+        // plain read instead of queueing on the counter's atomic
+        first = false;
+        uint32_t seen = 0;
+        if (lane == 0) seen = __hip_atomic_load(a.ctl + kCtlNext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (uniform(seen) >= nb) break;
+      }
       uint32_t k = 0;
       if (lane == 0) k = atomicAdd(a.ctl + kCtlNext, 1u);
       k = uniform(k);

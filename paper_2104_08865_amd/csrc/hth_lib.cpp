@@ -203,10 +203,11 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 // Planner and hashing kernel of one batch on `stream`, using workspace `w`.
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
-                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop) {
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves) {
   uint32_t grid = 0;
   hth_status st = grid_for(out_width, &grid);
   if (st != HTH_OK) return st;
+  if (max_waves && max_waves < grid) grid = (uint32_t)max_waves;
   Tuning tune;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -250,6 +251,11 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   if (e != hipSuccess) return hip_fail(e, "main launch");
   if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;
+}
+
+uint64_t task_bound(uint64_t len, uint32_t out_width) {
+  const uint64_t n = len / hth::exec_bytes_of(out_width);
+  return n ? (n + 127) / 128 : 1;
 }
 
 // Synchronise and read a workspace's planner status word.

@@ -207,9 +207,10 @@ bool launch_batch(hth_server* s, uint32_t si) {
     sl.out_at[w] = out_at;
     out_at += n[w] * (uint64_t)(16 + 8 * w);
   }
-  uint64_t fillw[kWidths] = {};
+  uint64_t fillw[kWidths] = {}, waves[kWidths] = {};
   for (const Request& r : sl.reqs) {
     const int w = widx(r.width);
+    waves[w] += task_bound(r.len, r.width);
     sl.h_meta[meta_at[w] + fillw[w]] = r.dev_pos % s->dev.cap;
     sl.h_meta[meta_at[w] + n[w] + fillw[w]] = r.len;
     ++fillw[w];
@@ -242,7 +243,7 @@ bool launch_batch(hth_server* s, uint32_t si) {
     if (!n[w]) continue;
     const uint64_t* d_off = sl.d_meta + meta_at[w];
     hth_status st = enqueue_batch(s->seed, s->d_ring, d_off, d_off + n[w], n[w], sl.d_out + sl.out_at[w],
-                                  (uint32_t)(16 + 8 * w), sl.ws, sl.stream, nullptr, nullptr);
+                                  (uint32_t)(16 + 8 * w), sl.ws, sl.stream, nullptr, nullptr, waves[w]);
     if (st != HTH_OK) {
       set_failed(s, hipErrorLaunchFailure, "batch launch");
       return false;
