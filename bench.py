@@ -42,6 +42,8 @@ WIDTHS = (16, 24, 32, 40)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2104_08865_amd", "csrc", "hth_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hash_main_throughput_traffic.json")
+UNEVEN_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hash_main_uneven_traffic.json")
+DEFAULT_CHOICES = ((0, 0, 5), (8, 0, 5))  # the launch choice the uneven counters were taken with
 
 
 def log(msg):
@@ -53,11 +55,11 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(width):
-    """HBM bytes per launch from the committed counter summary, if it was
+def measured_traffic(width, path=None):
+    """HBM bytes per launch from a committed counter summary, if it was
     taken on the current kernel source."""
     try:
-        doc = json.load(open(TRAFFIC_FILE))
+        doc = json.load(open(path or TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if doc.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -106,6 +108,9 @@ def run_main():
     ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve"), default="throughput")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per offered load (serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
+    ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default launch choice")
+    ap.add_argument("--no-per-string", action="store_true",
+                    help="uneven workload: skip the per-string launch comparison (for profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -336,10 +341,7 @@ def run_uneven(args):
     """200,000 log-uniform lengths in [16 B, 256 KiB) plus every length 0..520
     (bytes from splitmix64 seed 3, packed back to back, so most strings start
     unaligned), width 24."""
-    import ctypes
-
     import torch
-    import oracle
     from paper_2104_08865_amd import autotune, hth
     from paper_2104_08865_amd import workloads as wl
 
@@ -355,7 +357,11 @@ def run_uneven(args):
     n = torch.from_numpy(lens.view(np.int64)).to(dev)
     seed = hth.expand_seed(3)
     hth.reserve(count)
-    choice, times = autotune.tune(seed, data, o, n, width, total_bytes=total, use_cache=False)
+    if args.no_autotune:
+        choice, times = (0, 0, 5), {}
+        hth.set_tuning(width)
+    else:
+        choice, times = autotune.tune(seed, data, o, n, width, total_bytes=total, use_cache=False)
     log(f"[bench] autotuned launch choice (waves/CU, min level, max level) = {choice}")
     out = torch.empty((count, width), dtype=torch.uint8, device=dev)
 
@@ -378,7 +384,21 @@ def run_uneven(args):
     g.check()
     graph_out = g.out.cpu().numpy()
 
-    # one launch of the same library call per string
+    if args.no_per_string:
+        swall, per_out = None, persistent
+    else:
+        swall, per_out = _per_string(hth, torch, seed, data, o, n, width, count, dev)
+    agree = bool((persistent == graph_out).all() and (persistent == per_out).all())
+    pstr = f"{total / swall / 1e9:.1f}" if swall else "skipped"
+    log(f"[bench] persistent {total / wall * args.steps / 1e9:.0f} GB/s, graph {total / gwall * args.steps / 1e9:.0f} "
+        f"GB/s, per-string {pstr} GB/s, identical={agree}")
+    return _uneven_line(args, total, count, wall, gwall, swall, kernel_ms, width, choice, times, agree, persistent,
+                        lens, offs)
+
+
+def _per_string(hth, torch, seed, data, o, n, width, count, dev):
+    """The same library call once per string (one launch each)."""
+    import ctypes
     L = hth.lib()
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     per = torch.empty((count, width), dtype=torch.uint8, device=dev)
@@ -393,11 +413,13 @@ def run_uneven(args):
             raise RuntimeError(L.hth_last_error())
     torch.cuda.synchronize()
     swall = time.perf_counter() - t0
-    per_out = per.cpu().numpy()
-    agree = bool((persistent == graph_out).all() and (persistent == per_out).all())
-    log(f"[bench] persistent {total / wall * args.steps / 1e9:.0f} GB/s, graph {total / gwall * args.steps / 1e9:.0f} "
-        f"GB/s, per-string {total / swall / 1e9:.1f} GB/s, identical={agree}")
+    return swall, per.cpu().numpy()
 
+
+def _uneven_line(args, total, count, wall, gwall, swall, kernel_ms, width, choice, times, agree, persistent, lens,
+                 offs):
+    import oracle
+    from paper_2104_08865_amd import workloads as wl
     cpu = None
     if not args.no_cpu_baseline:
         idx = np.arange(0, count, 20)
@@ -422,10 +444,11 @@ def run_uneven(args):
                                "0..520, packed back to back (splitmix64 seed 3), width 24, one persistent launch",
                    "strings": int(count), "bytes": int(total), "width": width, "seed": 3,
                    "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
-        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms),
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms,
+                              measured_traffic(width, UNEVEN_TRAFFIC_FILE) if choice in DEFAULT_CHOICES else None),
         "graph_replay_GBps": total * args.steps / gwall / 1e9,
-        "per_string_launches_GBps": total / swall / 1e9,
-        "persistent_over_per_string": (total * args.steps / wall) / (total / swall),
+        "per_string_launches_GBps": total / swall / 1e9 if swall else None,
+        "persistent_over_per_string": (total * args.steps / wall) / (total / swall) if swall else None,
         "all_three_identical": agree,
         "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
         "cpu_baseline": cpu,
