@@ -100,8 +100,9 @@ hth_status hth_seed_free(hth_seed *seed);
  *   out_width  16, 24, 32 or 40.
  *
  * out[i] depends only on the seed and string i, never on the rest of the
- * batch.  The call enqueues a short planning step and one persistent kernel
- * on `stream` and returns.  Scratch memory comes from a per-stream workspace
+ * batch.  The call enqueues a short planning step, one persistent hashing
+ * kernel and a small kernel for the strings shorter than one EHC execution
+ * (tail only) on `stream` and returns.  Scratch memory comes from a per-stream workspace
  * that the library grows on the host as `count` grows (hth_reserve
  * pre-allocates it, e.g. before stream capture: a call inside a capture never
  * allocates and fails with HTH_E_INVALID if the workspace is too small).
@@ -116,8 +117,9 @@ hth_status hth_hash_batch(const hth_seed *seed, const uint8_t *bytes, const uint
 
 /* hth_hash_batch, and also record `main_start` and `main_stop` (events the
    caller created with hipEventCreate; either may be null) on `stream`
-   immediately before and after the hashing kernel, so that the caller can
-   time that kernel alone (the planning step runs before main_start).
+   immediately before and after the hashing (the persistent kernel and the
+   tail-only kernel), so that the caller can time it without the planning
+   step, which runs before main_start.
    Same arguments, errors and semantics as hth_hash_batch otherwise. */
 hth_status hth_hash_batch_timed(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
                                 const uint64_t *lengths, uint64_t count, uint8_t *out,

@@ -30,6 +30,7 @@ struct Workspace {
   uint32_t* task_start = nullptr;
   uint32_t* acc_start = nullptr;
   uint32_t* bucket_lead = nullptr;
+  uint32_t* tiny_list = nullptr;
   uint64_t* sacc = nullptr;
   uint32_t* sdone = nullptr;
   uint64_t* gacc = nullptr;

@@ -20,6 +20,11 @@ constexpr uint32_t kMaxBuckets = 1u << 16;
 constexpr uint64_t kMinBucketBytes = 128u << 10;
 constexpr uint64_t kTaskOverheadBytes = 4096;
 constexpr int kPlanSums = 3;  // per candidate task size: tasks, accumulators, work
+// Per planner block: kPlanSums per candidate, then the block's tail-only strings.
+constexpr int kBlockSums = kPlanCandidates * kPlanSums + 1;
+// Tail-only strings (shorter than one EHC execution) get no task: they are
+// listed apart and hashed one string per lane, kTinyChunk strings per fetch.
+constexpr int kTinyChunk = 64;
 
 // Control words of one launch (device memory, written by the planner).
 enum {
@@ -28,6 +33,8 @@ enum {
   kCtlLevel,
   kCtlError,
   kCtlBuckets,   // number of buckets (leaders)
+  kCtlTiny,      // number of tail-only strings
+  kCtlTinyNext,  // next chunk of tail-only strings to hand out
   kCtlWords = 16
 };
 
@@ -35,7 +42,7 @@ struct PlanArgs {
   const uint64_t* lengths;
   uint64_t count;
   uint32_t exec_bytes;
-  uint64_t* block_sums;  // [nblocks][kPlanCandidates][kPlanSums]
+  uint64_t* block_sums;  // [nblocks][kBlockSums]
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
@@ -43,6 +50,7 @@ struct PlanArgs {
   uint32_t* task_start;   // [count]
   uint32_t* acc_start;    // [count]
   uint32_t* bucket_lead;  // [kMaxBuckets]: leader task of each bucket, any order
+  uint32_t* tiny_list;    // [count]: the tail-only strings
   uint32_t* ctl;          // [kCtlWords]
 };
 
@@ -60,6 +68,7 @@ struct MainArgs {
   uint64_t* gacc;  // [cap_accs][kMaxK * 8], zero between launches
   uint32_t* gcnt;  // [cap_accs], zero between launches
   const uint32_t* bucket_lead;
+  const uint32_t* tiny_list;
   uint32_t* ctl;
 };
 
@@ -69,6 +78,7 @@ int64_t entropy_offset_of(uint32_t width);
 uint64_t entropy_words_total();
 uint64_t plan_block_count(uint64_t count);
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
+// The hashing kernel, then the tail-only kernel, both with `grid` waves.
 hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream);
 
 }  // namespace hth

@@ -190,9 +190,10 @@ __device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_e
 
 // Per string and per candidate task size 128 * 8^j: number of tasks, and
 // number of cross-task accumulators (complete nodes of levels >= j + 3).
+// A tail-only string (N = 0) has no task: it is hashed from the tiny list.
 __device__ __forceinline__ void plan_counts(uint64_t N, int j, uint64_t& tasks, uint64_t& accs) {
   const int shift = 7 + 3 * j;
-  tasks = N ? ((N + (1ull << shift) - 1) >> shift) : 1;
+  tasks = (N + (1ull << shift) - 1) >> shift;
   accs = 0;
   for (int l = j + 3; l < 22; ++l) accs += nodes_at(N, l);
 }
@@ -252,13 +253,13 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
 // accumulators and work of its kPlanBlock strings.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
                                 uint32_t exec_bytes, uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t lds[kPlanWaves][kPlanCandidates * kPlanSums];
+  __shared__ uint64_t lds[kPlanWaves][kBlockSums];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t L[kPlanPer];
   for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
-  uint64_t v[kPlanCandidates * kPlanSums];
+  uint64_t v[kBlockSums];
   for (int j = 0; j < kPlanCandidates; ++j) {
     uint64_t t = 0, a = 0, w = 0;
     for (int i = 0; i < kPlanPer; ++i) {
@@ -267,18 +268,21 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
       plan_counts(L[i] / exec_bytes, j, ti, ai);
       t += ti;
       a += ai;
-      w += L[i] + kTaskOverheadBytes * ti;
+      w += ti ? L[i] + kTaskOverheadBytes * ti : 0;
     }
     v[j * kPlanSums + 0] = t;
     v[j * kPlanSums + 1] = a;
     v[j * kPlanSums + 2] = w;
   }
+  uint64_t tiny = 0;
+  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && L[i] < exec_bytes;
+  v[kBlockSums - 1] = tiny;
   block_sum_n(v, lds);
-  if (threadIdx.x < kPlanCandidates * kPlanSums) {
+  if (threadIdx.x < kBlockSums) {
     uint64_t x = v[0];
-    for (int k = 1; k < kPlanCandidates * kPlanSums; ++k)
+    for (int k = 1; k < kBlockSums; ++k)
       if ((int)threadIdx.x == k) x = v[k];
-    block_sums[(uint64_t)blk * kPlanCandidates * kPlanSums + threadIdx.x] = x;
+    block_sums[(uint64_t)blk * kBlockSums + threadIdx.x] = x;
   }
 }
 
@@ -288,18 +292,18 @@ __device__ void plan_fill_body(
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
-    uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
-  __shared__ uint64_t ldsn[kPlanWaves][kPlanCandidates * kPlanSums];
-  __shared__ uint64_t lds3[kPlanWaves][kPlanSums];
+  __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
+  __shared__ uint64_t lds4[kPlanWaves][kPlanSums + 1];
   __shared__ uint32_t incl[kPlanBlock];
   __shared__ uint64_t wstart[kPlanBlock];
   const int tid = threadIdx.x;
   // Totals of every candidate over all blocks (threads stride over blocks).
-  uint64_t tot[kPlanCandidates * kPlanSums];
-  for (int k = 0; k < kPlanCandidates * kPlanSums; ++k) tot[k] = 0;
+  uint64_t tot[kBlockSums];
+  for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
   for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
-    for (int k = 0; k < kPlanCandidates * kPlanSums; ++k) tot[k] += block_sums[(uint64_t)b * kPlanCandidates * kPlanSums + k];
+    for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
   block_sum_n(tot, ldsn);
   uint64_t tt[kPlanCandidates], ta[kPlanCandidates], tw[kPlanCandidates];
   for (int j = 0; j < kPlanCandidates; ++j) {
@@ -325,35 +329,47 @@ __device__ void plan_fill_body(
     ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
     ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
     ctl[kCtlError] = jsel >= 0 ? 0 : 1;
+    ctl[kCtlTiny] = jsel >= 0 ? (uint32_t)tot[kBlockSums - 1] : 0;
+    ctl[kCtlTinyNext] = 0;
   }
   if (jsel < 0) return;  // uniform over the grid
-  // Tasks, accumulators and work of the blocks before this one.
-  uint64_t pre[kPlanSums] = {0, 0, 0};
-  for (uint32_t b = tid; b < blk; b += kPlanThreads)
-    for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[((uint64_t)b * kPlanCandidates + jsel) * kPlanSums + k];
-  block_sum_n(pre, lds3);
+  // Tasks, accumulators, work and tail-only strings of the blocks before this one.
+  uint64_t pre[kPlanSums + 1] = {0, 0, 0, 0};
+  for (uint32_t b = tid; b < blk; b += kPlanThreads) {
+    for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)b * kBlockSums + jsel * kPlanSums + k];
+    pre[kPlanSums] += block_sums[(uint64_t)b * kBlockSums + kBlockSums - 1];
+  }
+  block_sum_n(pre, lds4);
   const uint64_t task_base = pre[0];
   const uint64_t acc_base = pre[1];
   const uint64_t work_base = pre[2];
+  const uint64_t tiny_base = pre[3];
 
   const uint64_t base = (uint64_t)blk * kPlanBlock + tid * kPlanPer;
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
-  uint64_t st = 0, sa = 0, sw = 0;
+  uint64_t st = 0, sa = 0, sw = 0, sy = 0;
+  bool tiny[kPlanPer];
   for (int i = 0; i < kPlanPer; ++i) {
     tk[i] = ac[i] = wk[i] = 0;
+    tiny[i] = false;
     if (base + i < count) {
       const uint64_t L = lengths[base + i];
       plan_counts(L / exec_bytes, jsel, tk[i], ac[i]);
-      wk[i] = L + kTaskOverheadBytes * tk[i];
+      wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
+      tiny[i] = L < exec_bytes;
     }
     st += tk[i];
     sa += ac[i];
     sw += wk[i];
+    sy += tiny[i];
   }
-  uint64_t blk_t, blk_a, blk_w;
+  uint64_t blk_t, blk_a, blk_w, blk_y;
   const uint64_t et = block_exclusive(st, lds, blk_t);
   const uint64_t ea = block_exclusive(sa, lds, blk_a);
   const uint64_t ew = block_exclusive(sw, lds, blk_w);
+  uint64_t ty = tiny_base + block_exclusive(sy, lds, blk_y);
+  for (int i = 0; i < kPlanPer; ++i)
+    if (tiny[i]) tiny_list[ty++] = (uint32_t)(base + i);
   uint64_t run_t = task_base + et, run_a = acc_base + ea, run_w = work_base + ew;
   uint64_t loc = et;
   for (int i = 0; i < kPlanPer; ++i) {
@@ -370,12 +386,11 @@ __device__ void plan_fill_body(
   }
   __syncthreads();
   // Fill the task -> string table for this block's tasks.  A task leads a
-  // bucket when a bucket boundary k * bucket falls in (start of the task
-  // before it, its own start]: the buckets are the runs of tasks from one
-  // leader to the next, each starting at the first task that begins at or
-  // after a boundary, so no bucket is empty.  Leaders carry bit 31 in the
-  // table and are appended to bucket_lead (in no particular order) with one
-  // atomic per workgroup.
+  // bucket when a bucket boundary k * bucket falls inside its work
+  // [start, end): the buckets are the runs of tasks from one leader to the
+  // next, so none is empty and there are at most as many as boundaries.
+  // Leaders carry bit 31 in the table and are appended to bucket_lead (in no
+  // particular order) with one atomic per workgroup.
   const uint64_t first = (uint64_t)blk * kPlanBlock;
   const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
   const uint64_t texec = 128ull << (3 * jsel);
@@ -390,21 +405,12 @@ __device__ void plan_fill_body(
     }
     const uint64_t task = task_base + e;
     const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
+    const uint64_t L = lengths[first + lo];
+    uint64_t ntk, nac;
+    plan_counts(L / exec_bytes, jsel, ntk, nac);
     const uint64_t w0 = wstart[lo] + tau * unit;
-    bool lead = task == 0;
-    if (!lead) {
-      uint64_t wprev;  // start of the task before this one
-      if (tau > 0) {
-        wprev = w0 - unit;
-      } else {
-        // last task of the previous string (possibly another workgroup's)
-        const uint64_t Lp = lengths[first + lo - 1];
-        uint64_t ntp, nap;
-        plan_counts(Lp / exec_bytes, jsel, ntp, nap);
-        wprev = w0 - (Lp + kTaskOverheadBytes * ntp - (ntp - 1) * unit);
-      }
-      lead = w0 / bucket > wprev / bucket;
-    }
+    const uint64_t w1 = tau + 1 < ntk ? w0 + unit : wstart[lo] + L + kTaskOverheadBytes * ntk;
+    const bool lead = (w0 + bucket - 1) / bucket * bucket < w1;
     task_string[task] = (uint32_t)(first + lo) | (lead ? 0x80000000u : 0u);
     nlead += lead;
   }
@@ -434,9 +440,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
-    uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
   plan_fill_body(blockIdx.x, lengths, count, exec_bytes, block_sums, nblocks, cap_tasks, cap_accs, min_j, max_j,
-                 target_tasks, task_string, task_start, acc_start, bucket_lead, ctl);
+                 target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
 // Both steps in one workgroup, for batches of at most kPlanBlock strings
@@ -446,11 +452,11 @@ __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint64_t* __restrict__ block_sums,
     uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j, uint64_t target_tasks,
     uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
-    uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
   plan_count_body(0, lengths, count, exec_bytes, block_sums, ctl);
   __syncthreads();
   plan_fill_body(0, lengths, count, exec_bytes, block_sums, 1, cap_tasks, cap_accs, min_j, max_j, target_tasks,
-                 task_string, task_start, acc_start, bucket_lead, ctl);
+                 task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -672,6 +678,75 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
   }
 }
 
+// One tail-only string: its tail words hashed with the Toeplitz keys of
+// §6.1 plus the length term, by one lane.
+template <int WIDTH>
+__device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
+  using Ly = Layout<WIDTH>;
+  constexpr int K = Family<WIDTH>::K;
+  const uint64_t* __restrict__ ent = a.ent;
+  const uint64_t L = a.lengths[s];
+  const uint8_t* __restrict__ str = a.bytes + a.offsets[s];
+  uint64_t F[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) F[t] = 0;
+  // whole 128-byte groups: eight independent 16-byte loads, then 16 words
+  uint64_t m = 0;
+  for (; 8 * m + 128 <= L; m += 16) {
+    uint64_t w[16];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) __builtin_memcpy(&w[2 * c], str + 8 * m + 16 * c, 16);
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+#pragma unroll
+      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[c], ent[Ly::tail + t + m + c]);
+  }
+  // remaining whole words, then the zero-padded last word
+  for (; 8 * m + 8 <= L; ++m) {
+    uint64_t w;
+    __builtin_memcpy(&w, str + 8 * m, 8);
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+  }
+  if (L & 7) {
+    uint64_t w = 0;
+    for (uint64_t b = 0; b < (L & 7); ++b) w |= (uint64_t)str[8 * m + b] << (8 * b);
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+  }
+  uint8_t* o = a.out + (uint64_t)s * WIDTH;
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const uint64_t v = nh_acc(F[t], L, ent[Ly::len + t]);
+    __builtin_memcpy(o + 8 * t, &v, 8);
+  }
+}
+
+// Tail-only strings (shorter than one execution: §6.1's tail and the length
+// term, no tree), one string per lane, in chunks of kTinyChunk strings taken
+// from a device counter.  A separate kernel: inside the hashing kernel this
+// code cost the full passes 3-10 % (register allocation of the whole
+// kernel), while a launch costs a few microseconds.
+template <int WIDTH>
+__global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
+  const int lane = threadIdx.x;
+  const uint32_t ntiny = uniform(a.ctl[kCtlTiny]);
+  const uint32_t nchunks = (ntiny + kTinyChunk - 1) / kTinyChunk;
+  // most waves of a grid larger than the work leave on a plain read
+  uint32_t seen = 0;
+  if (lane == 0) seen = __hip_atomic_load(a.ctl + kCtlTinyNext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (uniform(seen) >= nchunks) return;
+  for (;;) {
+    __builtin_amdgcn_wave_barrier();
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(a.ctl + kCtlTinyNext, 1u);
+    k = uniform(k);
+    if (k >= nchunks) return;
+    const uint32_t idx = k * kTinyChunk + (uint32_t)lane;
+    if (idx < ntiny) tiny_one<WIDTH>(a, a.tiny_list[idx]);
+  }
+}
+
 template <int WIDTH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void hash_main_kernel(MainArgs a) {
   using Fm = Family<WIDTH>;
@@ -865,6 +940,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     fetch = (next_entry >> 31) != 0;
     __builtin_amdgcn_wave_barrier();
   }
+
 }
 
 // ---------------------------------------------------------------------------
@@ -904,7 +980,7 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   if (nblocks == 1) {
     hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
                        p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
-                       p.task_start, p.acc_start, p.bucket_lead, p.ctl);
+                       p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
@@ -913,16 +989,29 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
                      p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
-                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.ctl);
+                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream) {
+  // the hashing kernel, then the tail-only strings
   switch (width) {
-    case 16: hipLaunchKernelGGL(hash_main_kernel<16>, dim3(grid), dim3(64), 0, stream, a); break;
-    case 24: hipLaunchKernelGGL(hash_main_kernel<24>, dim3(grid), dim3(64), 0, stream, a); break;
-    case 32: hipLaunchKernelGGL(hash_main_kernel<32>, dim3(grid), dim3(64), 0, stream, a); break;
-    case 40: hipLaunchKernelGGL(hash_main_kernel<40>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 16:
+      hipLaunchKernelGGL(hash_main_kernel<16>, dim3(grid), dim3(64), 0, stream, a);
+      hipLaunchKernelGGL(tiny_kernel<16>, dim3(grid), dim3(64), 0, stream, a);
+      break;
+    case 24:
+      hipLaunchKernelGGL(hash_main_kernel<24>, dim3(grid), dim3(64), 0, stream, a);
+      hipLaunchKernelGGL(tiny_kernel<24>, dim3(grid), dim3(64), 0, stream, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL(hash_main_kernel<32>, dim3(grid), dim3(64), 0, stream, a);
+      hipLaunchKernelGGL(tiny_kernel<32>, dim3(grid), dim3(64), 0, stream, a);
+      break;
+    case 40:
+      hipLaunchKernelGGL(hash_main_kernel<40>, dim3(grid), dim3(64), 0, stream, a);
+      hipLaunchKernelGGL(tiny_kernel<40>, dim3(grid), dim3(64), 0, stream, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -86,10 +86,11 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
     return at;
   };
   size_t o_ctl = take(hth::kCtlWords * 4);
-  size_t o_bs = take(n.cap_blocks * hth::kPlanSums * hth::kPlanCandidates * 8);
+  size_t o_bs = take(n.cap_blocks * hth::kBlockSums * 8);
   size_t o_ts = take(n.cap_tasks * 4);
   size_t o_st = take(n.cap_count * 4);
   size_t o_as = take(n.cap_count * 4);
+  size_t o_tl = take(n.cap_count * 4);
   size_t o_bf = take(((size_t)hth::kMaxBuckets + 2) * 4);
   size_t o_sacc = take(n.cap_count * hth::kMaxK * 8);
   size_t o_sdone = take(n.cap_count * 4);
@@ -110,6 +111,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   n.task_string = reinterpret_cast<uint32_t*>(b + o_ts);
   n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
   n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
+  n.tiny_list = reinterpret_cast<uint32_t*>(b + o_tl);
   n.bucket_lead = reinterpret_cast<uint32_t*>(b + o_bf);
   n.sacc = reinterpret_cast<uint64_t*>(b + o_sacc);
   n.sdone = reinterpret_cast<uint32_t*>(b + o_sdone);
@@ -227,6 +229,7 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   p.task_start = w.task_start;
   p.acc_start = w.acc_start;
   p.bucket_lead = w.bucket_lead;
+  p.tiny_list = w.tiny_list;
   p.ctl = w.ctl;
   hipError_t e = hth::launch_plan(p, stream);
   if (e != hipSuccess) return hip_fail(e, "plan launch");
@@ -245,6 +248,7 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.gacc = w.gacc;
   a.gcnt = w.gcnt;
   a.bucket_lead = w.bucket_lead;
+  a.tiny_list = w.tiny_list;
   a.ctl = w.ctl;
   if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
   e = hth::launch_main(out_width, a, grid, stream);
