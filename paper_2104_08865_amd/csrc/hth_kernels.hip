@@ -69,6 +69,10 @@ __device__ __forceinline__ uint64_t mulc(int c, uint64_t h) {
 // data's waits) and keep the keys out of vector registers.
 typedef const __attribute__((address_space(4))) uint64_t* key_ptr;
 __device__ __forceinline__ key_ptr uniform_keys(const uint64_t* p) { return (key_ptr)p; }
+// The same for per-string metadata read at wave-uniform indices (written
+// before the launch, read-only during it).
+typedef const __attribute__((address_space(4))) uint32_t* meta32_ptr;
+__device__ __forceinline__ meta32_ptr smeta(const uint32_t* p) { return (meta32_ptr)p; }
 
 __device__ __forceinline__ uint4 load16(const uint8_t* p) {
   uint4 v;
@@ -775,6 +779,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const uint32_t ntasks_all = uniform(a.ctl[kCtlTotal]);
   uint32_t task = 0;
   bool fetch = true, first = true;
+  // metadata of the next task's string, read while the current task runs
+  bool have_next = false;
+  uint32_t pf_s = 0, pf_ts = 0, pf_as = 0;
+  uint64_t pf_off = 0, pf_L = 0;
   for (;;) {
     __builtin_amdgcn_wave_barrier();
     if (fetch) {
@@ -792,111 +800,169 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       if (k >= nb) break;
       task = uniform(a.bucket_lead[k]);
       fetch = false;
+      have_next = false;
+      continue;  // (an empty bucket would fetch again)
     }
-    const uint32_t s = uniform(a.task_string[task]) & 0x7FFFFFFFu;
-    // next task's entry, read early: whether it leads another bucket
-    const uint32_t next_entry = task + 1 < ntasks_all ? uniform(a.task_string[task + 1]) : 0x80000000u;
-    const uint64_t tau = task - uniform(a.task_start[s]);
-    const uint64_t off = uniform64(a.offsets[s]);
-    const uint64_t L = uniform64(a.lengths[s]);
+    uint32_t s, ts, as;
+    uint64_t off, L;
+    if (have_next) {
+      s = pf_s;
+      ts = pf_ts;
+      as = pf_as;
+      off = pf_off;
+      L = pf_L;
+    } else {
+      s = smeta(a.task_string)[task] & 0x7FFFFFFFu;
+      ts = smeta(a.task_start)[s];
+      as = smeta(a.acc_start)[s];
+      off = uniform_keys(a.offsets)[s];
+      L = uniform_keys(a.lengths)[s];
+    }
+    // next task's entry: whether it leads another bucket; if not, its
+    // string's metadata is read now and used next time round
+    const uint32_t next_entry = task + 1 < ntasks_all ? smeta(a.task_string)[task + 1] : 0x80000000u;
+    have_next = (next_entry >> 31) == 0;
+    if (have_next) {
+      pf_s = next_entry;
+      pf_ts = smeta(a.task_start)[pf_s];
+      pf_as = smeta(a.acc_start)[pf_s];
+      pf_off = uniform_keys(a.offsets)[pf_s];
+      pf_L = uniform_keys(a.lengths)[pf_s];
+    }
+    const uint64_t tau = task - ts;
     const uint64_t N = L / XB;
     const uint64_t ntask = N ? (N + texec - 1) / texec : 1;
     const uint8_t* __restrict__ str = a.bytes + off;
 
-    Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)uniform(a.acc_start[s]) : 0, a.gacc, a.gcnt};
+    Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)as : 0, a.gacc, a.gcnt};
     uint64_t F[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = 0;
 
-    const uint64_t g0 = tau * texec;
-    const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
-    for (uint64_t p = g0; p < g1; p += 128) {
-      if (N - p < 128) {
-        // the string's last, partial pass
-        partial_pass<WIDTH>(c, str, p, (uint32_t)(N - p), F, lacc);
-        break;
-      }
-      // full pass: lane group q takes the 8 consecutive executions
-      // p + 8q .. p + 8q + 7, i.e. all children of level-1 node p/8 + q
-      uint64_t a0[K], a1[K];
-#pragma unroll
-      for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
-      const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
-      for (int e = 0; e < 8; ++e) {
-        uint64_t z0[K], z1[K];
-        ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
-        // level 0 of every tree: child e of this lane's level-1 node
-        if (e < kFan - 1) {
-#pragma unroll
-          for (int t = 0; t < K; ++t) {
-            const uint64_t key = uniform_keys(ent)[Ly::tree + (t * kLevels) * (kFan - 1) + e];
-            a0[t] = nh_acc(a0[t], z0[t], key);
-            a1[t] = nh_acc(a1[t], z1[t], key);
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t < K; ++t) {
-            a0[t] += z0[t];
-            a1[t] += z1[t];
-          }
-        }
-      }
-      // level 1 -> level 2: lane group q holds level-1 node p/8 + q, child
-      // pos1 of level-2 node p/64 + q/8
-      const int pos1 = q & 7;
-      uint64_t n0[K], n1[K];
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        uint64_t t0, t1;
-        if (pos1 < kFan - 1) {
-          const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
-          t0 = nh_acc(0, a0[t], key);
-          t1 = nh_acc(0, a1[t], key);
-        } else {
-          t0 = a0[t];
-          t1 = a1[t];
-        }
-        t0 += shfl_xor64(t0, 4);
-        t1 += shfl_xor64(t1, 4);
-        t0 += shfl_xor64(t0, 8);
-        t1 += shfl_xor64(t1, 8);
-        t0 += shfl_xor64(t0, 16);
-        t1 += shfl_xor64(t1, 16);
-        n0[t] = t0;
-        n1[t] = t1;
-      }
-      // lanes 0..3 hold level-2 node A (executions p .. p+63), lanes 32..35
-      // node B (p+64 .. p+127)
-      const uint64_t nA = p >> 6;
-      uint64_t b0[K], b1[K];
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        b0[t] = shfl64(n0[t], (lane & 3) + 32);
-        b1[t] = shfl64(n1[t], (lane & 3) + 32);
-      }
-      fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
-      fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
-    }
-
-    if (tau == ntask - 1) {
-      // tail (§6.1): words m0 .. m0+R-1, output t keyed by S_tail[t + m]
+    if (N < 128) {
+      // a string of fewer than 128 executions (one task): its tail words
+      // are loaded together with its data, then one partial pass
       const uint64_t tb = N * XB;
       const uint64_t rem = L - tb;
-      const uint64_t R = (rem + 7) / 8;
-      for (uint64_t m = lane; m < R; m += 64) {
-        uint64_t w = 0;
-        const uint8_t* pw = str + tb + 8 * m;
-        if (8 * m + 8 <= rem) {
-          __builtin_memcpy(&w, pw, 8);
-        } else {
-          for (uint64_t b = 0; b < rem - 8 * m; ++b) w |= (uint64_t)pw[b] << (8 * b);
-        }
+      const uint64_t R = (rem + 7) / 8;  // at most XB / 8 <= 3 * 64 words
+      uint64_t tw[3];
 #pragma unroll
-        for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+      for (int i = 0; i < 3; ++i) {
+        const uint64_t m = (uint64_t)lane + 64 * i;
+        tw[i] = 0;
+        if (m < R) {
+          const uint8_t* pw = str + tb + 8 * m;
+          if (8 * m + 8 <= rem) {
+            __builtin_memcpy(&tw[i], pw, 8);
+          } else {
+            for (uint64_t b = 0; b < rem - 8 * m; ++b) tw[i] |= (uint64_t)pw[b] << (8 * b);
+          }
+        }
+      }
+      if (N) partial_pass<WIDTH>(c, str, 0, (uint32_t)N, F, lacc);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const uint64_t m = (uint64_t)lane + 64 * i;
+        if (m < R) {
+#pragma unroll
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], tw[i], ent[Ly::tail + t + m]);
+        }
       }
       if (lane == 0) {
 #pragma unroll
         for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ent[Ly::len + t]);
+      }
+    } else {
+      const uint64_t g0 = tau * texec;
+      const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
+      for (uint64_t p = g0; p < g1; p += 128) {
+        if (N - p < 128) {
+          // the string's last, partial pass
+          partial_pass<WIDTH>(c, str, p, (uint32_t)(N - p), F, lacc);
+          break;
+        }
+        // full pass: lane group q takes the 8 consecutive executions
+        // p + 8q .. p + 8q + 7, i.e. all children of level-1 node p/8 + q
+        uint64_t a0[K], a1[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
+        const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
+        for (int e = 0; e < 8; ++e) {
+          uint64_t z0[K], z1[K];
+          ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
+          // level 0 of every tree: child e of this lane's level-1 node
+          if (e < kFan - 1) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+              const uint64_t key = uniform_keys(ent)[Ly::tree + (t * kLevels) * (kFan - 1) + e];
+              a0[t] = nh_acc(a0[t], z0[t], key);
+              a1[t] = nh_acc(a1[t], z1[t], key);
+            }
+          } else {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+              a0[t] += z0[t];
+              a1[t] += z1[t];
+            }
+          }
+        }
+        // level 1 -> level 2: lane group q holds level-1 node p/8 + q, child
+        // pos1 of level-2 node p/64 + q/8
+        const int pos1 = q & 7;
+        uint64_t n0[K], n1[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          uint64_t t0, t1;
+          if (pos1 < kFan - 1) {
+            const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
+            t0 = nh_acc(0, a0[t], key);
+            t1 = nh_acc(0, a1[t], key);
+          } else {
+            t0 = a0[t];
+            t1 = a1[t];
+          }
+          t0 += shfl_xor64(t0, 4);
+          t1 += shfl_xor64(t1, 4);
+          t0 += shfl_xor64(t0, 8);
+          t1 += shfl_xor64(t1, 8);
+          t0 += shfl_xor64(t0, 16);
+          t1 += shfl_xor64(t1, 16);
+          n0[t] = t0;
+          n1[t] = t1;
+        }
+        // lanes 0..3 hold level-2 node A (executions p .. p+63), lanes 32..35
+        // node B (p+64 .. p+127)
+        const uint64_t nA = p >> 6;
+        uint64_t b0[K], b1[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          b0[t] = shfl64(n0[t], (lane & 3) + 32);
+          b1[t] = shfl64(n1[t], (lane & 3) + 32);
+        }
+        fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
+        fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
+      }
+
+      if (tau == ntask - 1) {
+        // tail (§6.1): words m0 .. m0+R-1, output t keyed by S_tail[t + m]
+        const uint64_t tb = N * XB;
+        const uint64_t rem = L - tb;
+        const uint64_t R = (rem + 7) / 8;
+        for (uint64_t m = lane; m < R; m += 64) {
+          uint64_t w = 0;
+          const uint8_t* pw = str + tb + 8 * m;
+          if (8 * m + 8 <= rem) {
+            __builtin_memcpy(&w, pw, 8);
+          } else {
+            for (uint64_t b = 0; b < rem - 8 * m; ++b) w |= (uint64_t)pw[b] << (8 * b);
+          }
+#pragma unroll
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ent[Ly::len + t]);
+        }
       }
     }
 
