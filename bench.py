@@ -68,30 +68,55 @@ def measured_traffic(width, path=None):
     return None if row is None else row.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def pinned_oracle(fn):
+    """Run fn() pinned to one host core (restored afterwards); returns
+    (result, seconds, core)."""
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t0, core
+    finally:
+        os.sched_setaffinity(0, prev)
+
+
 def cpu_baseline(gpu_out, n_strings, string_bytes, sample_per_width):
     import oracle
     from paper_2104_08865_amd import workloads as wl
     ent = oracle.expand_seed(2)
     total_bytes, total_s, exact = 0, 0.0, True
+    idx = np.linspace(0, n_strings - 1, sample_per_width).astype(np.int64)
+    data = np.concatenate([wl.random_bytes(2, string_bytes, start_byte=int(i) * string_bytes) for i in idx])
+    offs = (np.arange(idx.size, dtype=np.uint64) * np.uint64(string_bytes))
+    lens = np.full(idx.size, string_bytes, dtype=np.uint64)
     for width in WIDTHS:
-        idx = np.linspace(0, n_strings - 1, sample_per_width).astype(np.int64)
-        data = np.concatenate([wl.random_bytes(2, string_bytes, start_byte=int(i) * string_bytes) for i in idx])
-        offs = (np.arange(idx.size, dtype=np.uint64) * np.uint64(string_bytes))
-        lens = np.full(idx.size, string_bytes, dtype=np.uint64)
-        t0 = time.perf_counter()
-        ref = oracle.hash_batch(ent, data, offs, lens, width, nthreads=1)
-        total_s += time.perf_counter() - t0
+        ref, dt, core = pinned_oracle(lambda: oracle.hash_batch(ent, data, offs, lens, width, nthreads=1))
+        total_s += dt
         total_bytes += data.size
         exact &= bool((gpu_out[width][idx] == ref).all())
-        log(f"[bench] cpu oracle width {width}: {idx.size} strings checked, exact={exact}")
+        log(f"[bench] cpu oracle width {width}: {idx.size} strings checked in {dt:.1f} s, exact={exact}")
     return {
         "value": total_bytes / total_s / 1e9,
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{sample_per_width} of the 4096 1 MiB strings at each width 16/24/32/40 "
-                  f"({total_bytes / 2**20:.0f} MiB), single thread",
+                  f"({total_bytes / 2**20:.0f} MiB hashed), single thread pinned to core {core}",
         "seconds": total_s,
+        "cpu_model": cpu_model(),
+        "host_cpus": len(os.sched_getaffinity(0)),
         "bit_exact_vs_gpu": exact,
     }
 
@@ -99,10 +124,10 @@ def cpu_baseline(gpu_out, n_strings, string_bytes, sample_per_width):
 def run_main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=384, help="oracle strings per width")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="oracle strings per width")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve"), default="throughput")
@@ -177,17 +202,28 @@ def run_throughput(args):
     value = step_bytes * args.steps / wall / 1e9
     per_width = {}
     for w in WIDTHS:
-        ms = float(np.mean([t.elapsed_ms() for t in timers[w]]))
+        samples = [t.elapsed_ms() for t in timers[w]]
+        ms = float(np.mean(samples))
         algo = n * sz + 16 * n + w * n  # input bytes + offsets/lengths + output
         achieved = algo / (ms * 1e-3) / 1e9
         per_width[str(w)] = {
             "kernel": f"hth::hash_main_kernel<{w}>",
             "avg_ms": ms,
+            "median_ms": float(np.median(samples)),
+            "median_GBps": algo / (float(np.median(samples)) * 1e-3) / 1e9,
             "algorithmic_bytes": algo,
             "achieved_GBps": achieved,
             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(w),
         }
+    # the device's plain streaming-read rate over the same 4 GiB buffer
+    probe = [hth.Timer() for _ in range(5)]
+    hth.read_probe(data)
+    for t in probe:
+        hth.read_probe(data, timer=t)
+    read_ms = float(np.median([t.elapsed_ms() for t in probe]))
+    read_ceiling = data.numel() / (read_ms * 1e-3) / 1e9
+    log(f"[bench] read-stream ceiling {read_ceiling:.0f} GB/s")
     dom = max(WIDTHS, key=lambda w: per_width[str(w)]["avg_ms"])
     d = per_width[str(dom)]
     roofline = {
@@ -200,6 +236,8 @@ def run_throughput(args):
         "kernel": d["kernel"],
         "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
         "avg_launch_ms": d["avg_ms"],
+        "read_stream_ceiling_GBps": read_ceiling,
+        "frac_of_read_stream_ceiling": d["achieved_GBps"] / read_ceiling,
     }
 
     cpu = None

@@ -165,6 +165,16 @@ hth_status hth_reserve(uint64_t max_count, hipStream_t stream);
    HTH_OK, or HTH_E_TOO_LARGE if the device rejected its size. */
 hth_status hth_batch_check(hipStream_t stream);
 
+/* Diagnostic: a plain streaming read of `bytes` (rounded down to 16-byte
+   pieces) of the device buffer buf (16-byte aligned), the achievable HBM
+   read rate that the hashing kernel is measured against.  Runs 8 waves per
+   compute unit (two workgroups of 256 threads; the rate is highest there),
+   at most one workgroup per word of the device array sink (sink_words >= 1;
+   its words are XOR-ed with the data read, so the caller zeroes it first).
+   Enqueued on `stream`.  Errors: HTH_E_INVALID, HTH_E_HIP. */
+hth_status hth_read_probe(const void *buf, uint64_t bytes, uint64_t *sink, uint32_t sink_words,
+                          hipStream_t stream);
+
 /* Tuning of the batched kernel for one output width; applies to later calls.
    waves_per_cu: resident single-wave workgroups per compute unit of the
    persistent grid (0 = the default, 8, or the occupancy limit if lower).  A task covers

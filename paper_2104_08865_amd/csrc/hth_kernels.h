@@ -77,6 +77,8 @@ uint32_t exec_bytes_of(uint32_t width);
 int64_t entropy_offset_of(uint32_t width);
 uint64_t entropy_words_total();
 uint64_t plan_block_count(uint64_t count);
+// Reads n16 16-byte pieces of buf; sink holds `blocks` words (XOR-folded).
+hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint32_t blocks, hipStream_t stream);
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
 // The hashing kernel, then the tail-only kernel, both with `grid` waves.
 hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream);

@@ -1010,6 +1010,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 }
 
 // ---------------------------------------------------------------------------
+// Read-bandwidth probe: the achievable HBM read rate on this device, the
+// ceiling the hashing kernel is compared with.  Every 16-byte piece of the
+// buffer is read once (grid-stride, four independent loads per lane in
+// flight) and folded into an XOR that is written out, so no load is dead.
+// ---------------------------------------------------------------------------
+
+constexpr int kProbeThreads = 256;
+
+__global__ __launch_bounds__(kProbeThreads) void read_probe_kernel(const uint4* __restrict__ p, uint64_t n16,
+                                                                   uint64_t* __restrict__ sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * kProbeThreads;
+  uint64_t i = (uint64_t)blockIdx.x * kProbeThreads + threadIdx.x;
+  uint32_t x = 0;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+    x ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
+  for (; i < n16; i += stride) {
+    const uint4 a = p[i];
+    x ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  for (int m = 32; m >= 1; m >>= 1) x ^= __shfl_xor(x, m);
+  if ((threadIdx.x & 63) == 0) atomicXor(reinterpret_cast<unsigned int*>(sink + blockIdx.x), x);
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 
@@ -1084,5 +1110,11 @@ hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStre
 }
 
 uint64_t plan_block_count(uint64_t count) { return (count + kPlanBlock - 1) / kPlanBlock; }
+
+hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint32_t blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(read_probe_kernel, dim3(blocks), dim3(kProbeThreads), 0, stream,
+                     reinterpret_cast<const uint4*>(buf), n16, sink);
+  return hipGetLastError();
+}
 
 }  // namespace hth

@@ -448,6 +448,21 @@ hth_status hth_batch_graph_free(hth_batch_graph* graph) {
   return HTH_OK;
 }
 
+hth_status hth_read_probe(const void* buf, uint64_t bytes, uint64_t* sink, uint32_t sink_words, hipStream_t stream) {
+  if (!buf || !sink || !sink_words) return fail(HTH_E_INVALID, "hth_read_probe: null pointer or empty sink");
+  if (reinterpret_cast<uintptr_t>(buf) % 16) return fail(HTH_E_INVALID, "hth_read_probe: buf not 16-byte aligned");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device attribute");
+  // 8 waves per compute unit (2 workgroups of 4 waves): the rate peaks there
+  uint32_t blocks = (uint32_t)cus * 2;
+  if (blocks > sink_words) blocks = sink_words;
+  e = hth::launch_read_probe(buf, bytes / 16, sink, blocks, stream);
+  if (e != hipSuccess) return hip_fail(e, "read probe launch");
+  return HTH_OK;
+}
+
 hth_status hth_batch_check(hipStream_t stream) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);

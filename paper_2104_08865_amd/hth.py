@@ -29,7 +29,7 @@ SYMBOLS = (
     "hth_batch_check", "hth_set_tuning", "hth_batch_graph_create", "hth_batch_graph_launch",
     "hth_batch_graph_check", "hth_batch_graph_free", "hth_serve_create", "hth_serve_submit",
     "hth_serve_poll", "hth_serve_wait", "hth_serve_wait_many", "hth_serve_replay", "hth_serve_stats",
-    "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause",
+    "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause", "hth_read_probe",
 )
 
 
@@ -96,6 +96,7 @@ def lib():
         L.hth_serve_reset_stats.argtypes = [vp]
         L.hth_serve_destroy.argtypes = [vp]
         L.hth_serve_pause.argtypes = [vp, ctypes.c_int32]
+        L.hth_read_probe.argtypes = [vp, u64, vp, u32, vp]
         for name in SYMBOLS[2:]:
             getattr(L, name).restype = ctypes.c_int32
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
@@ -177,7 +178,8 @@ def batch_check(stream=None):
 
 
 class Timer:
-    """A pair of HIP events (via the HIP runtime) around the hashing kernel."""
+    """A pair of HIP events (via the HIP runtime) around the hashing kernels
+    (or any enqueued work, with record_start / record_stop)."""
 
     _hip = None
 
@@ -188,10 +190,19 @@ class Timer:
             Timer._hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
             Timer._hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
             Timer._hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+            Timer._hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         self.start = ctypes.c_void_p()
         self.stop = ctypes.c_void_p()
         if Timer._hip.hipEventCreate(ctypes.byref(self.start)) or Timer._hip.hipEventCreate(ctypes.byref(self.stop)):
             raise RuntimeError("hipEventCreate failed")
+
+    def record_start(self, stream=None):
+        if Timer._hip.hipEventRecord(self.start, _stream(stream)):
+            raise RuntimeError("hipEventRecord failed")
+
+    def record_stop(self, stream=None):
+        if Timer._hip.hipEventRecord(self.stop, _stream(stream)):
+            raise RuntimeError("hipEventRecord failed")
 
     def elapsed_ms(self):
         ms = ctypes.c_float()
@@ -231,6 +242,20 @@ def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None, t
     else:
         _check(lib().hth_hash_batch_timed(*args, timer.start, timer.stop))
     return out
+
+
+def read_probe(data, sink_words=2048, stream=None, timer=None):
+    """Stream-read a 16-byte aligned uint8 CUDA tensor once (the device's
+    achievable HBM read rate); returns the sink tensor."""
+    import torch
+    sink = torch.zeros(sink_words, dtype=torch.int64, device=data.device)
+    if timer is not None:
+        timer.record_start(stream)
+    _check(lib().hth_read_probe(ctypes.c_void_p(data.data_ptr()), data.numel(), ctypes.c_void_p(sink.data_ptr()),
+                                sink_words, _stream(stream)))
+    if timer is not None:
+        timer.record_stop(stream)
+    return sink
 
 
 class BatchGraph:
