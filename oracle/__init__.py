@@ -58,6 +58,14 @@ def lib():
         L.hth_ref_hash_batch.argtypes = [u64p, ctypes.c_size_t, u8p, u64p, u64p, ctypes.c_uint64,
                                          ctypes.c_uint32, u8p, ctypes.c_uint32]
         L.hth_ref_mul_counts.argtypes = [u64p]
+        L.hth_ref_entropy_words_b.restype = ctypes.c_uint64
+        L.hth_ref_entropy_words_b.argtypes = [ctypes.c_uint32]
+        L.hth_ref_entropy_offset_b.restype = ctypes.c_int64
+        L.hth_ref_entropy_offset_b.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.hth_ref_expand_seed_b.argtypes = [ctypes.c_uint64, ctypes.c_uint32, u64p]
+        L.hth_ref_hash_b.argtypes = [u64p, ctypes.c_size_t, u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u8p]
+        L.hth_ref_hash_batch_b.argtypes = [u64p, ctypes.c_size_t, u8p, u64p, u64p, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint32]
         _lib = L
     return _lib
 
@@ -101,17 +109,18 @@ def layout(width, b=8, f=8):
     return [int(x) for x in out]
 
 
-def entropy_words():
-    return int(lib().hth_ref_entropy_words())
+def entropy_words(b=8):
+    """Entropy words of the standard layout for block size b (4 or 8)."""
+    return int(lib().hth_ref_entropy_words_b(b))
 
 
-def entropy_offset(width):
-    return int(lib().hth_ref_entropy_offset(width))
+def entropy_offset(width, b=8):
+    return int(lib().hth_ref_entropy_offset_b(width, b))
 
 
-def expand_seed(user_seed):
-    out = np.zeros(entropy_words(), dtype=np.uint64)
-    lib().hth_ref_expand_seed(ctypes.c_uint64(user_seed & (2**64 - 1)), _p64(out))
+def expand_seed(user_seed, b=8):
+    out = np.zeros(entropy_words(b), dtype=np.uint64)
+    lib().hth_ref_expand_seed_b(ctypes.c_uint64(user_seed & (2**64 - 1)), b, _p64(out))
     return out
 
 
@@ -163,19 +172,19 @@ def hash_words(width, entropy_block, words, n_exec=None, len_value=None, W=32, b
     return out
 
 
-def hash_bytes(entropy, data, width):
-    """The real family on one byte string; returns width bytes."""
+def hash_bytes(entropy, data, width, b=8):
+    """The real family (block size b) on one byte string; returns width bytes."""
     ent = _u64(entropy)
     data = np.ascontiguousarray(np.frombuffer(bytes(data), dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else data, dtype=np.uint8)
     out = np.zeros(width, dtype=np.uint8)
     dp = _p8(data) if data.size else ctypes.POINTER(ctypes.c_uint8)()
-    if lib().hth_ref_hash(_p64(ent), ent.size, dp, data.size, width, _p8(out)):
+    if lib().hth_ref_hash_b(_p64(ent), ent.size, dp, data.size, width, b, _p8(out)):
         raise ValueError("hth_ref_hash rejected its arguments")
     return out
 
 
-def hash_batch(entropy, data, offsets, lengths, width, nthreads=1):
-    """Many strings of one buffer; returns (count, width) uint8."""
+def hash_batch(entropy, data, offsets, lengths, width, nthreads=1, b=8):
+    """Many strings of one buffer (block size b); returns (count, width) uint8."""
     ent = _u64(entropy)
     data = np.ascontiguousarray(data, dtype=np.uint8)
     offsets = _u64(offsets); lengths = _u64(lengths)
@@ -184,8 +193,8 @@ def hash_batch(entropy, data, offsets, lengths, width, nthreads=1):
     if count:
         assert int((offsets + lengths).max()) <= data.size
     dp = _p8(data) if data.size else ctypes.POINTER(ctypes.c_uint8)()
-    if lib().hth_ref_hash_batch(_p64(ent), ent.size, dp, _p64(offsets), _p64(lengths), count,
-                                width, _p8(out), nthreads):
+    if lib().hth_ref_hash_batch_b(_p64(ent), ent.size, dp, _p64(offsets), _p64(lengths), count,
+                                  width, b, _p8(out), nthreads):
         raise ValueError("hth_ref_hash_batch rejected its arguments")
     return out
 

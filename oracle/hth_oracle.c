@@ -135,32 +135,38 @@ int hth_ref_layout(uint32_t out_width, uint32_t b, uint32_t f, uint64_t offs[6])
     return 0;
 }
 
-uint64_t hth_ref_entropy_words(void)
+/* The standard layout for block size b: the four widths' blocks back to
+   back, in the order 16, 24, 32, 40.  b = 8 is the 512-bit block of the
+   paper's default variant, b = 4 the 256-bit one (§6.3: b follows the
+   vector width of the machine, and each b is its own family). */
+static int block_ok(uint32_t b) { return b == 4 || b == 8; }
+
+uint64_t hth_ref_entropy_words_b(uint32_t b)
 {
+    if (!block_ok(b)) return 0;
     uint64_t total = 0, offs[6];
     for (int i = 0; i < 4; i++) {
-        hth_ref_layout(SHAPES[i].width, HTH_REF_B, HTH_REF_F, offs);
+        hth_ref_layout(SHAPES[i].width, b, HTH_REF_F, offs);
         total += offs[5];
     }
     return total;
 }
-
-int64_t hth_ref_entropy_offset(uint32_t out_width)
+int64_t hth_ref_entropy_offset_b(uint32_t out_width, uint32_t b)
 {
+    if (!block_ok(b)) return -1;
     uint64_t at = 0, offs[6];
     for (int i = 0; i < 4; i++) {
         if (SHAPES[i].width == out_width) return (int64_t)at;
-        hth_ref_layout(SHAPES[i].width, HTH_REF_B, HTH_REF_F, offs);
+        hth_ref_layout(SHAPES[i].width, b, HTH_REF_F, offs);
         at += offs[5];
     }
     return -1;
 }
-
-/* splitmix64 (Steele, Lea and Flood, OOPSLA 2014): the state advances by the
-   golden-ratio increment and each output is a finaliser of the new state. */
-void hth_ref_expand_seed(uint64_t user_seed, uint64_t *words)
+uint64_t hth_ref_entropy_words(void) { return hth_ref_entropy_words_b(HTH_REF_B); }
+int64_t hth_ref_entropy_offset(uint32_t out_width) { return hth_ref_entropy_offset_b(out_width, HTH_REF_B); }
+void hth_ref_expand_seed_b(uint64_t user_seed, uint32_t b, uint64_t *words)
 {
-    uint64_t n = hth_ref_entropy_words();
+    uint64_t n = hth_ref_entropy_words_b(b);
     uint64_t state = user_seed;
     for (uint64_t i = 0; i < n; i++) {
         state += 0x9E3779B97F4A7C15ULL;
@@ -170,6 +176,7 @@ void hth_ref_expand_seed(uint64_t user_seed, uint64_t *words)
         words[i] = z ^ (z >> 31);
     }
 }
+void hth_ref_expand_seed(uint64_t user_seed, uint64_t *words) { hth_ref_expand_seed_b(user_seed, HTH_REF_B, words); }
 
 /* ------------------------------------------------------------------------ */
 /* Arithmetic.                                                               */
@@ -469,11 +476,11 @@ int hth_ref_hash_words(uint32_t out_width, uint32_t W, uint32_t b, uint32_t f, c
     return hash_words(sh, W, b, f, entropy, words, nwords, n_exec, len_value, recursive, out);
 }
 
-int hth_ref_hash(const uint64_t *entropy, size_t n_words, const uint8_t *data, uint64_t len,
-                 uint32_t out_width, uint8_t *out)
+int hth_ref_hash_b(const uint64_t *entropy, size_t n_words, const uint8_t *data, uint64_t len,
+                   uint32_t out_width, uint32_t b, uint8_t *out)
 {
     const ref_shape *sh = shape_of(out_width);
-    if (!sh || !entropy || !out || n_words != hth_ref_entropy_words()) return -1;
+    if (!sh || !block_ok(b) || !entropy || !out || n_words != hth_ref_entropy_words_b(b)) return -1;
     if (len && !data) return -1;
     /* words: little-endian 64-bit, the last one zero padded */
     uint64_t nw = (len + 7) / 8;
@@ -489,16 +496,21 @@ int hth_ref_hash(const uint64_t *entropy, size_t n_words, const uint8_t *data, u
     }
     /* full executions are counted in bytes, so a final partial word never
        completes an execution */
-    uint64_t xb = 8ULL * HTH_REF_B * sh->d * HTH_REF_W;
+    uint64_t xb = 8ULL * b * sh->d * HTH_REF_W;
     uint64_t n_exec = len / xb;
     uint64_t z[5];
-    const uint64_t *ent = entropy + hth_ref_entropy_offset(out_width);
-    int rc = hash_words(sh, 32, HTH_REF_B, HTH_REF_F, ent, words, nw, n_exec, len, 0, z);
+    const uint64_t *ent = entropy + hth_ref_entropy_offset_b(out_width, b);
+    int rc = hash_words(sh, 32, b, HTH_REF_F, ent, words, nw, n_exec, len, 0, z);
     free(words);
     if (rc) return rc;
     for (unsigned t = 0; t < sh->k; t++)
         for (unsigned q = 0; q < 8; q++) out[t * 8 + q] = (uint8_t)(z[t] >> (8 * q));
     return 0;
+}
+int hth_ref_hash(const uint64_t *entropy, size_t n_words, const uint8_t *data, uint64_t len,
+                 uint32_t out_width, uint8_t *out)
+{
+    return hth_ref_hash_b(entropy, n_words, data, len, out_width, HTH_REF_B, out);
 }
 
 void hth_ref_mul_counts(uint64_t out[5])
@@ -516,7 +528,7 @@ typedef struct {
     const uint8_t *data;
     const uint64_t *offsets, *lengths;
     uint64_t count;
-    uint32_t out_width;
+    uint32_t out_width, b;
     uint8_t *out;
     uint32_t nthreads, id;
     int rc;
@@ -527,24 +539,24 @@ static void *batch_worker(void *arg)
     batch_job *jb = arg;
     jb->rc = 0;
     for (uint64_t i = jb->id; i < jb->count; i += jb->nthreads) {
-        int rc = hth_ref_hash(jb->entropy, jb->n_words, jb->data + jb->offsets[i], jb->lengths[i],
-                              jb->out_width, jb->out + i * jb->out_width);
+        int rc = hth_ref_hash_b(jb->entropy, jb->n_words, jb->data + jb->offsets[i], jb->lengths[i],
+                                jb->out_width, jb->b, jb->out + i * jb->out_width);
         if (rc) jb->rc = rc;
     }
     return NULL;
 }
 
-int hth_ref_hash_batch(const uint64_t *entropy, size_t n_words, const uint8_t *data,
-                       const uint64_t *offsets, const uint64_t *lengths, uint64_t count,
-                       uint32_t out_width, uint8_t *out, uint32_t nthreads)
+int hth_ref_hash_batch_b(const uint64_t *entropy, size_t n_words, const uint8_t *data,
+                         const uint64_t *offsets, const uint64_t *lengths, uint64_t count,
+                         uint32_t out_width, uint32_t b, uint8_t *out, uint32_t nthreads)
 {
-    if (!shape_of(out_width) || (count && (!offsets || !lengths || !out))) return -1;
+    if (!shape_of(out_width) || !block_ok(b) || (count && (!offsets || !lengths || !out))) return -1;
     if (nthreads == 0) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     batch_job jobs[256];
     pthread_t th[256];
     for (uint32_t i = 0; i < nthreads; i++) {
-        jobs[i] = (batch_job){entropy, n_words, data, offsets, lengths, count, out_width, out,
+        jobs[i] = (batch_job){entropy, n_words, data, offsets, lengths, count, out_width, b, out,
                               nthreads, i, 0};
         if (nthreads == 1) batch_worker(&jobs[i]);
         else pthread_create(&th[i], NULL, batch_worker, &jobs[i]);
@@ -555,4 +567,11 @@ int hth_ref_hash_batch(const uint64_t *entropy, size_t n_words, const uint8_t *d
         if (jobs[i].rc) rc = jobs[i].rc;
     }
     return rc;
+}
+int hth_ref_hash_batch(const uint64_t *entropy, size_t n_words, const uint8_t *data,
+                       const uint64_t *offsets, const uint64_t *lengths, uint64_t count,
+                       uint32_t out_width, uint8_t *out, uint32_t nthreads)
+{
+    return hth_ref_hash_batch_b(entropy, n_words, data, offsets, lengths, count, out_width, HTH_REF_B, out,
+                                nthreads);
 }

@@ -100,6 +100,22 @@ int hth_ref_hash_batch(const uint64_t *entropy, size_t n_words,
                        const uint64_t *lengths, uint64_t count,
                        uint32_t out_width, uint8_t *out, uint32_t nthreads);
 
+/* The same for block size b = 4 or 8 (§6.3: b is the machine's vector width
+   in 64-bit words, and each b defines its own family; b = 8 is the standard
+   layout above).  The layout for b has the four widths' blocks of
+   hth_ref_layout(width, b, 8) back to back; the seed expansion fills it from
+   one splitmix64 stream.  Invalid b: 0 words / offset -1 / status -1. */
+uint64_t hth_ref_entropy_words_b(uint32_t b);
+int64_t hth_ref_entropy_offset_b(uint32_t out_width, uint32_t b);
+void hth_ref_expand_seed_b(uint64_t user_seed, uint32_t b, uint64_t *words);
+int hth_ref_hash_b(const uint64_t *entropy, size_t n_words, const uint8_t *data,
+                   uint64_t len, uint32_t out_width, uint32_t b, uint8_t *out);
+int hth_ref_hash_batch_b(const uint64_t *entropy, size_t n_words,
+                         const uint8_t *data, const uint64_t *offsets,
+                         const uint64_t *lengths, uint64_t count,
+                         uint32_t out_width, uint32_t b, uint8_t *out,
+                         uint32_t nthreads);
+
 /* Multiplication counters of the last hth_ref_hash_words / hth_ref_hash call
    on this thread: {ehc, tree, final, tail, length}. */
 void hth_ref_mul_counts(uint64_t out[5]);

@@ -23,30 +23,34 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "hth_golden.json"
 
 
 def cases():
-    for width in (16, 24, 32, 40):
-        xb = wl.execution_bytes(width)
-        lens = [0, 1, 7, 8, 9, 63, 64, 100, 1024, xb - 8, xb - 1, xb, xb + 1, 8 * xb - 1, 8 * xb,
-                8 * xb + 1, 9 * xb + 17, 64 * xb - 1, 64 * xb, 64 * xb + 1, 65 * xb + 8 * xb + 3,
-                512 * xb + 5]
-        for user_seed in (1, 0x0123456789ABCDEF):
-            for n in lens:
-                yield user_seed, width, n
+    for b in (8, 4):
+        for width in (16, 24, 32, 40):
+            xb = wl.execution_bytes(width) * b // 8
+            lens = [0, 1, 7, 8, 9, 63, 64, 100, 1024, xb - 8, xb - 1, xb, xb + 1, 8 * xb - 1, 8 * xb,
+                    8 * xb + 1, 9 * xb + 17, 64 * xb - 1, 64 * xb, 64 * xb + 1, 65 * xb + 8 * xb + 3,
+                    512 * xb + 5]
+            for user_seed in (1, 0x0123456789ABCDEF):
+                for n in lens:
+                    yield b, user_seed, width, n
 
 
 def main():
     rows = []
     ents = {}
-    for user_seed, width, n in cases():
-        if user_seed not in ents:
-            ents[user_seed] = oracle.expand_seed(user_seed)
+    for b, user_seed, width, n in cases():
+        if (b, user_seed) not in ents:
+            ents[(b, user_seed)] = oracle.expand_seed(user_seed, b=b)
         data = wl.random_bytes(1, n)
-        h = oracle.hash_bytes(ents[user_seed], data.tobytes(), width)
-        rows.append({"user_seed": user_seed, "width": width, "length": n, "bytes_seed": 1,
-                     "hash": bytes(h).hex()})
+        h = oracle.hash_bytes(ents[(b, user_seed)], data.tobytes(), width, b=b)
+        row = {"user_seed": user_seed, "width": width, "length": n, "bytes_seed": 1, "hash": bytes(h).hex()}
+        if b != 8:
+            row["block_words"] = b
+        rows.append(row)
     doc = {
         "about": "HalftimeHash values of the frozen family, written by tests/golden/make_golden.py "
                  "from the CPU oracle; data = first `length` bytes of the splitmix64 byte buffer "
-                 "with seed `bytes_seed`; entropy = splitmix64 expansion of `user_seed`.",
+                 "with seed `bytes_seed`; entropy = splitmix64 expansion of `user_seed`; "
+                 "`block_words` (default 8) is the family's block size b.",
         "cases": rows,
     }
     with open(OUT, "w") as f:

@@ -12,9 +12,9 @@ def test_oracle_matches_golden(oracle_lib):
     doc = json.load(open(GOLDEN))
     ents = {}
     for row in doc["cases"]:
-        s = row["user_seed"]
-        if s not in ents:
-            ents[s] = oracle_lib.expand_seed(s)
+        s, b = row["user_seed"], row.get("block_words", 8)
+        if (s, b) not in ents:
+            ents[(s, b)] = oracle_lib.expand_seed(s, b=b)
         data = wl.random_bytes(row["bytes_seed"], row["length"])
-        h = oracle_lib.hash_bytes(ents[s], data.tobytes(), row["width"])
+        h = oracle_lib.hash_bytes(ents[(s, b)], data.tobytes(), row["width"], b=b)
         assert bytes(h).hex() == row["hash"], row

@@ -546,3 +546,105 @@ def test_entropy_formula_reproduces_paper_figure():
     words = e * w + (f - 1) * h * k + b * f * h * k + b * d * w + k - 1
     assert n_exec == 780 and h == 4
     assert round(words * 8 / 1000, 1) == 8.4
+
+
+# ---------------------------------------------------------------------------
+# The 256-bit block variant (b = 4; §6.3: b is the machine's vector width in
+# 64-bit words, and each b is its own family)
+# ---------------------------------------------------------------------------
+
+def _nh_py(x, s):
+    """NH of one word against one key, from the definition of §3.2 (halves
+    added separately mod 2^32, then multiplied)."""
+    lo = ((x & 0xFFFFFFFF) + (s & 0xFFFFFFFF)) & 0xFFFFFFFF
+    hi = ((x >> 32) + (s >> 32)) & 0xFFFFFFFF
+    return lo * hi
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_b4_layout_sizes(oracle_lib, width):
+    """With b = 4 the per-instance parts shrink to 4 instances: final keys
+    k * 20 levels * 7 positions * 4 instances, Toeplitz tail keys for the
+    longest tail (4*d*w words) plus k - 1; EHC and tree keys do not depend on
+    b; the four widths sit back to back."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    offs = o.layout(width, 4, 8)
+    sizes = np.diff(offs)
+    assert list(sizes) == [e * w, k * 20 * 7, k * 20 * 7 * 4, 4 * d * w + k - 1, k]
+    assert o.entropy_words(4) == sum(o.layout(x, 4, 8)[5] for x in WIDTHS)
+    assert o.entropy_offset(width, 4) == sum(o.layout(x, 4, 8)[5] for x in WIDTHS if x < width)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_b4_tail_only_closed_form(oracle_lib, width):
+    """A string shorter than one b = 4 execution (32*d*w bytes) is its tail:
+    out_t = sum_m NH(word_m, S_tail[t + m]) + NH(L, S_len[t]) with the b = 4
+    layout's keys; at exactly one execution it is not (the tree path runs)."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    ent = o.expand_seed(11, b=4)
+    base = o.entropy_offset(width, 4)
+    offs = o.layout(width, 4, 8)
+    xb = 32 * d * w
+    for L in (0, 1, 9, 200, xb - 1):
+        data = wl.random_bytes(12, L).tobytes()
+        words = [int.from_bytes(data[i:i + 8].ljust(8, b"\0"), "little") for i in range(0, L, 8)]
+        out = np.frombuffer(o.hash_bytes(ent, data, width, b=4).tobytes(), dtype="<u8")
+        for t in range(k):
+            acc = sum(_nh_py(x, int(ent[base + offs[3] + t + m])) for m, x in enumerate(words))
+            acc += _nh_py(L, int(ent[base + offs[4] + t]))
+            assert int(out[t]) == acc & M64, (L, t)
+    data = wl.random_bytes(12, xb).tobytes()
+    words = [int.from_bytes(data[i:i + 8], "little") for i in range(0, xb, 8)]
+    out = np.frombuffer(o.hash_bytes(ent, data, width, b=4).tobytes(), dtype="<u8")
+    tail_form = (sum(_nh_py(x, int(ent[base + offs[3] + m])) for m, x in enumerate(words))
+                 + _nh_py(xb, int(ent[base + offs[4]]))) & M64
+    assert int(out[0]) != tail_form
+    assert o.mul_counts()["ehc"] == e * w * 4
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_b4_multiplication_counts(oracle_lib, width):
+    """§6.1 counts with b = 4 on byte strings: e*w*b products per execution,
+    (f-1)*b per tree node per output, b per leftover item per output, one per
+    tail word per output, one per output for the length."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    b, f = 4, 8
+    ent = o.expand_seed(5, b=4)
+    xb = 8 * b * d * w
+    for n, extra in ((1, 0), (8, 17), (9, 1), (64, 0), (100, 301), (600, 8)):
+        L = n * xb + extra
+        o.hash_bytes(ent, wl.random_bytes(n, L).tobytes(), width, b=4)
+        c = o.mul_counts()
+        assert c["ehc"] == e * w * b * n
+        nodes = sum(n // f ** (l + 1) for l in range(20))
+        assert c["tree"] == k * b * (f - 1) * nodes
+        assert c["final"] == k * b * sum(_digits(n, f))
+        assert c["tail"] == k * ((extra + 7) // 8)
+        assert c["length"] == k
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_b4_zero_entropy_one_word(oracle_lib, width):
+    """b = 4, zero entropy, one execution with a single non-zero word at
+    (item c, sub-word u, instance j): the result is the b = 8 closed form with
+    the execution laid out as 4-word blocks (word index (c*w + u)*4 + j)."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    P, T = o.tables(width)
+    ent = np.zeros(o.entropy_words(4), dtype=np.uint64)
+    xw = 4 * d * w
+    a_, b_ = 0x12345679, 0x0FEDCBA9
+    for c, u, j in [(0, 0, 0), (d - 1, 2, 3), (1, 1, 2)]:
+        buf = np.zeros(xw, dtype=np.uint64)
+        buf[(c * w + u) * 4 + j] = np.uint64(a_ + (b_ << 32))
+        hcount = np.zeros(e, dtype=np.int64)
+        hcount[c] = 1
+        for r in range(k - 1):
+            hcount[d + r] = sum(_mbit(int(P[r][c]), uu, u) for uu in range(3))
+        out = np.frombuffer(o.hash_bytes(ent, buf.astype("<u8").tobytes(), width, b=4).tobytes(), dtype="<u8")
+        for t in range(k):
+            z = sum(int(T[t][q]) * int(hcount[q]) for q in range(e)) * (a_ * b_) & M64
+            assert int(out[t]) == ((z & 0xFFFFFFFF) * (z >> 32)) & M64, (c, u, j, t)
