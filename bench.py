@@ -92,17 +92,17 @@ def pinned_oracle(fn):
         os.sched_setaffinity(0, prev)
 
 
-def cpu_baseline(gpu_out, n_strings, string_bytes, sample_per_width):
+def cpu_baseline(gpu_out, n_strings, string_bytes, sample_per_width, b=8):
     import oracle
     from paper_2104_08865_amd import workloads as wl
-    ent = oracle.expand_seed(2)
+    ent = oracle.expand_seed(2, b=b)
     total_bytes, total_s, exact = 0, 0.0, True
     idx = np.linspace(0, n_strings - 1, sample_per_width).astype(np.int64)
     data = np.concatenate([wl.random_bytes(2, string_bytes, start_byte=int(i) * string_bytes) for i in idx])
     offs = (np.arange(idx.size, dtype=np.uint64) * np.uint64(string_bytes))
     lens = np.full(idx.size, string_bytes, dtype=np.uint64)
     for width in WIDTHS:
-        ref, dt, core = pinned_oracle(lambda: oracle.hash_batch(ent, data, offs, lens, width, nthreads=1))
+        ref, dt, core = pinned_oracle(lambda: oracle.hash_batch(ent, data, offs, lens, width, nthreads=1, b=b))
         total_s += dt
         total_bytes += data.size
         exact &= bool((gpu_out[width][idx] == ref).all())
@@ -134,6 +134,8 @@ def run_main():
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per offered load (serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
     ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default launch choice")
+    ap.add_argument("--block-words", type=int, default=8, choices=(4, 8),
+                    help="throughput workload: the family's block size b (8, or 4 for the 256-bit family)")
     ap.add_argument("--no-per-string", action="store_true",
                     help="uneven workload: skip the per-string launch comparison (for profiling runs)")
     args = ap.parse_args()
@@ -167,7 +169,8 @@ def run_throughput(args):
     data = wl.random_bytes_torch(2, n * sz, dev)
     offs = torch.arange(n, dtype=torch.int64, device=dev) * sz
     lens = torch.full((n,), sz, dtype=torch.int64, device=dev)
-    seed = hth.expand_seed(2)
+    b = args.block_words
+    seed = hth.expand_seed(2, block_words=b)
     outs = {w: torch.empty((n, w), dtype=torch.uint8, device=dev) for w in WIDTHS}
     hth.reserve(n)
     torch.cuda.synchronize()
@@ -214,7 +217,7 @@ def run_throughput(args):
             "algorithmic_bytes": algo,
             "achieved_GBps": achieved,
             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(w),
+            "traffic": measured_traffic(w) if b == 8 else None,
         }
     # the device's plain streaming-read rate over the same 4 GiB buffer
     probe = [hth.Timer() for _ in range(5)]
@@ -243,7 +246,7 @@ def run_throughput(args):
     cpu = None
     if not args.no_cpu_baseline:
         host_out = {w: outs[w].cpu().numpy() for w in WIDTHS}
-        cpu = cpu_baseline(host_out, n, sz, args.cpu_sample)
+        cpu = cpu_baseline(host_out, n, sz, args.cpu_sample, b)
 
     line = {
         "metric": "hashed GB/s vs HBM peak (bit-exact to oracle); p50/p99 latency at fixed rate",
@@ -260,11 +263,13 @@ def run_throughput(args):
         "data": "synthetic",
         "config": {
             "workload": "throughput batch: 4096 strings x 1 MiB, uniform random bytes (splitmix64 seed 2), "
-                        "hashed at widths 16/24/32/40 (one launch per width)",
+                        "hashed at widths 16/24/32/40 (one launch per width)"
+                        + ("" if b == 8 else f", {64 * b}-bit block family (b = {b})"),
             "strings": n,
             "string_bytes": sz,
             "widths": list(WIDTHS),
             "seed": 2,
+            "block_words": b,
         },
         "roofline": roofline,
         "per_width": per_width,

@@ -76,8 +76,24 @@ hth_status hth_expand_seed(uint64_t user_seed, hth_seed **out, hipStream_t strea
 hth_status hth_seed_from_entropy(const uint64_t *words, size_t n_words, hth_seed **out,
                                  hipStream_t stream);
 
-/* Copy a seed's entropy words to host memory (n_words must equal
-   hth_entropy_words()).  Synchronous. */
+/* The 256-bit block family.  §6.3 makes the block size b (64-bit words per
+   block) the machine's vector width, and each b its own family: b = 8 (the
+   default, used by the calls above) or b = 4, the paper's 256-bit variant.
+   With b = 4 an EHC execution is 32*d*w bytes (576 / 672 / 672 / 480 for
+   the widths 16 / 24 / 32 / 40), there are 4 instances, and the layout per
+   width is [EHC e*w][tree k*20*7][final k*20*7*4][tail 4*d*w + k - 1][len k].
+   A seed carries its b; hth_hash_batch, captured batches and servers hash
+   with the family of the seed they are given.  block_words must be 4 or 8
+   (HTH_E_INVALID otherwise); other errors as the b = 8 calls. */
+size_t hth_entropy_words_b(uint32_t block_words);
+hth_status hth_expand_seed_b(uint64_t user_seed, uint32_t block_words, hth_seed **out, hipStream_t stream);
+hth_status hth_seed_from_entropy_b(const uint64_t *words, size_t n_words, uint32_t block_words, hth_seed **out,
+                                   hipStream_t stream);
+/* Block size of a seed's family (0 for null). */
+uint32_t hth_seed_block_words(const hth_seed *seed);
+
+/* Copy a seed's entropy words to host memory (n_words must equal the
+   seed's entropy size).  Synchronous. */
 hth_status hth_seed_entropy(const hth_seed *seed, uint64_t *host_words, size_t n_words);
 
 /* Release a seed.  Work already enqueued with it must have completed.

@@ -72,28 +72,37 @@ constexpr unsigned gf8_mul(unsigned a, unsigned b) {
 // Does parity word u of (a * X) include input word v?
 constexpr bool image_bit(unsigned a, int u, int v) { return (gf8_mul(a, 1u << v) >> u) & 1u; }
 
-template <int WIDTH>
+// Entropy layout of one width for block size B (64-bit words per block:
+// 8 for the 512-bit family, 4 for the 256-bit one; §6.3): EHC keys, tree
+// keys, final keys (per instance), Toeplitz tail keys, length keys.
+template <int WIDTH, int B = kBlock>
 struct Layout {
   using F = Family<WIDTH>;
   static constexpr int ehc = 0;
   static constexpr int tree = ehc + F::E * kSym;
   static constexpr int fin = tree + F::K * kLevels * (kFan - 1);
-  static constexpr int tail = fin + F::K * kLevels * (kFan - 1) * kBlock;
-  static constexpr int len = tail + kBlock * F::D * kSym + F::K - 1;
+  static constexpr int tail = fin + F::K * kLevels * (kFan - 1) * B;
+  static constexpr int len = tail + B * F::D * kSym + F::K - 1;
   static constexpr int total = len + F::K;
-  static constexpr int exec_bytes = 8 * kBlock * F::D * kSym;
-  static constexpr int exec_words = kBlock * F::D * kSym;
+  static constexpr int exec_bytes = 8 * B * F::D * kSym;
+  static constexpr int exec_words = B * F::D * kSym;
 };
 
+// The four widths' blocks back to back, in the order 16, 24, 32, 40.
+template <int B = kBlock>
 constexpr int width_offset(int width) {
   return width == 16   ? 0
-         : width == 24 ? Layout<16>::total
-         : width == 32 ? Layout<16>::total + Layout<24>::total
-         : width == 40 ? Layout<16>::total + Layout<24>::total + Layout<32>::total
+         : width == 24 ? Layout<16, B>::total
+         : width == 32 ? Layout<16, B>::total + Layout<24, B>::total
+         : width == 40 ? Layout<16, B>::total + Layout<24, B>::total + Layout<32, B>::total
                        : -1;
 }
-constexpr int kEntropyWords =
-    Layout<16>::total + Layout<24>::total + Layout<32>::total + Layout<40>::total;
-static_assert(kEntropyWords == 18369, "entropy layout size");
+template <int B = kBlock>
+constexpr int entropy_words() {
+  return Layout<16, B>::total + Layout<24, B>::total + Layout<32, B>::total + Layout<40, B>::total;
+}
+constexpr int kEntropyWords = entropy_words<8>();
+static_assert(kEntropyWords == 18369, "entropy layout size, b = 8");
+static_assert(entropy_words<4>() == 10229, "entropy layout size, b = 4");
 
 }  // namespace hth

@@ -9,6 +9,7 @@
 
 struct hth_seed {
   int device = 0;
+  uint32_t block = 8;  // 64-bit words per block of the family (8 or 4)
   uint64_t* d_words = nullptr;
   std::vector<uint64_t> host;
 };
@@ -59,8 +60,8 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
                          hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0);
 
 // Upper bound of the tasks a string of `len` bytes can make (at the finest
-// task size), for max_waves.
-uint64_t task_bound(uint64_t len, uint32_t out_width);
+// task size) in the family with `block` words per block, for max_waves.
+uint64_t task_bound(uint64_t len, uint32_t out_width, uint32_t block);
 
 }  // namespace host
 }  // namespace hth

@@ -42,6 +42,7 @@ struct PlanArgs {
   const uint64_t* lengths;
   uint64_t count;
   uint32_t exec_bytes;
+  uint32_t pass_log2;     // log2 of the executions of one pass (7 for b = 8, 8 for b = 4)
   uint64_t* block_sums;  // [nblocks][kBlockSums]
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
@@ -72,15 +73,17 @@ struct MainArgs {
   uint32_t* ctl;
 };
 
-const void* main_kernel_fn(uint32_t width);
-uint32_t exec_bytes_of(uint32_t width);
-int64_t entropy_offset_of(uint32_t width);
-uint64_t entropy_words_total();
+// Kernels and layouts per (output width, block size b = 4 or 8).
+const void* main_kernel_fn(uint32_t width, uint32_t block);
+uint32_t exec_bytes_of(uint32_t width, uint32_t block);
+uint32_t pass_log2_of(uint32_t block);
+int64_t entropy_offset_of(uint32_t width, uint32_t block);
+uint64_t entropy_words_total(uint32_t block);
 uint64_t plan_block_count(uint64_t count);
 // Reads n16 16-byte pieces of buf; sink holds `blocks` words (XOR-folded).
 hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint32_t blocks, hipStream_t stream);
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
 // The hashing kernel, then the tail-only kernel, both with `grid` waves.
-hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream);
+hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
 
 }  // namespace hth

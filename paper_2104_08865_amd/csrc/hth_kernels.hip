@@ -123,17 +123,18 @@ __device__ __forceinline__ void complete_atomics() {
 __device__ __forceinline__ uint64_t nodes_at(uint64_t N, int l) { return l >= 22 ? 0 : N >> (3 * l); }
 
 // ---------------------------------------------------------------------------
-// EHC of one execution for the two instances of a lane.
+// EHC of one execution for the two instances of a lane (blocks of B words:
+// block i of the execution starts 8*B*i bytes in).
 // ---------------------------------------------------------------------------
 
-template <int WIDTH>
+template <int WIDTH, int B>
 __device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_ehc,
                                      uint64_t z0[], uint64_t z1[]) {
   using Fm = Family<WIDTH>;
   constexpr int D = Fm::D, K = Fm::K, R = K - 1;
   uint4 x[D * kSym];
 #pragma unroll
-  for (int i = 0; i < D * kSym; ++i) x[i] = load16(eb + 64 * i);
+  for (int i = 0; i < D * kSym; ++i) x[i] = load16(eb + 8 * B * i);
 
   uint64_t par0[R > 0 ? R : 1][kSym], par1[R > 0 ? R : 1][kSym];
 #pragma unroll
@@ -192,11 +193,13 @@ __device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_e
 // Planning kernels: tasks and cross-task accumulators per string.
 // ---------------------------------------------------------------------------
 
-// Per string and per candidate task size 128 * 8^j: number of tasks, and
+// Per string and per candidate task size 2^pass_log2 * 8^j executions (a
+// pass is 128 executions for b = 8, 256 for b = 4): number of tasks, and
 // number of cross-task accumulators (complete nodes of levels >= j + 3).
 // A tail-only string (N = 0) has no task: it is hashed from the tiny list.
-__device__ __forceinline__ void plan_counts(uint64_t N, int j, uint64_t& tasks, uint64_t& accs) {
-  const int shift = 7 + 3 * j;
+__device__ __forceinline__ void plan_counts(uint64_t N, int j, uint32_t pass_log2, uint64_t& tasks,
+                                            uint64_t& accs) {
+  const int shift = (int)pass_log2 + 3 * j;
   tasks = (N + (1ull << shift) - 1) >> shift;
   accs = 0;
   for (int l = j + 3; l < 22; ++l) accs += nodes_at(N, l);
@@ -256,7 +259,8 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
 // Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
 // accumulators and work of its kPlanBlock strings.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
-                                uint32_t exec_bytes, uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
+                                uint32_t exec_bytes, uint32_t pass_log2, uint64_t* __restrict__ block_sums,
+                                uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves][kBlockSums];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
@@ -269,7 +273,7 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     for (int i = 0; i < kPlanPer; ++i) {
       if (base + i >= count) continue;
       uint64_t ti, ai;
-      plan_counts(L[i] / exec_bytes, j, ti, ai);
+      plan_counts(L[i] / exec_bytes, j, pass_log2, ti, ai);
       t += ti;
       a += ai;
       w += ti ? L[i] + kTaskOverheadBytes * ti : 0;
@@ -292,7 +296,7 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
 
 // Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
 __device__ void plan_fill_body(
-    uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
+    uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
@@ -358,7 +362,7 @@ __device__ void plan_fill_body(
     tiny[i] = false;
     if (base + i < count) {
       const uint64_t L = lengths[base + i];
-      plan_counts(L / exec_bytes, jsel, tk[i], ac[i]);
+      plan_counts(L / exec_bytes, jsel, pass_log2, tk[i], ac[i]);
       wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
       tiny[i] = L < exec_bytes;
     }
@@ -397,7 +401,7 @@ __device__ void plan_fill_body(
   // particular order) with one atomic per workgroup.
   const uint64_t first = (uint64_t)blk * kPlanBlock;
   const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
-  const uint64_t texec = 128ull << (3 * jsel);
+  const uint64_t texec = 1ull << (pass_log2 + 3 * jsel);
   const uint64_t unit = texec * exec_bytes + kTaskOverheadBytes;  // work of a full task
   uint32_t nlead = 0;
   for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
@@ -411,7 +415,7 @@ __device__ void plan_fill_body(
     const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
     const uint64_t L = lengths[first + lo];
     uint64_t ntk, nac;
-    plan_counts(L / exec_bytes, jsel, ntk, nac);
+    plan_counts(L / exec_bytes, jsel, pass_log2, ntk, nac);
     const uint64_t w0 = wstart[lo] + tau * unit;
     const uint64_t w1 = tau + 1 < ntk ? w0 + unit : wstart[lo] + L + kTaskOverheadBytes * ntk;
     const bool lead = (w0 + bucket - 1) / bucket * bucket < w1;
@@ -434,18 +438,19 @@ __device__ void plan_fill_body(
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
                                                                   uint64_t count, uint32_t exec_bytes,
+                                                                  uint32_t pass_log2,
                                                                   uint64_t* __restrict__ block_sums,
                                                                   uint32_t* __restrict__ ctl) {
-  plan_count_body(blockIdx.x, lengths, count, exec_bytes, block_sums, ctl);
+  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, block_sums, ctl);
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
-    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes,
+    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, block_sums, nblocks, cap_tasks, cap_accs, min_j, max_j,
+  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, block_sums, nblocks, cap_tasks, cap_accs, min_j, max_j,
                  target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -453,13 +458,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
 // (one launch instead of two).  The barrier between the steps also makes
 // step 1's global writes visible to the whole workgroup.
 __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
-    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint64_t* __restrict__ block_sums,
-    uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j, uint64_t target_tasks,
+    const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
+    uint64_t* __restrict__ block_sums, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
+    uint64_t target_tasks,
     uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
     uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_count_body(0, lengths, count, exec_bytes, block_sums, ctl);
+  plan_count_body(0, lengths, count, exec_bytes, pass_log2, block_sums, ctl);
   __syncthreads();
-  plan_fill_body(0, lengths, count, exec_bytes, block_sums, 1, cap_tasks, cap_accs, min_j, max_j, target_tasks,
+  plan_fill_body(0, lengths, count, exec_bytes, pass_log2, block_sums, 1, cap_tasks, cap_accs, min_j, max_j, target_tasks,
                  task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -470,12 +476,28 @@ __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
 // Local accumulators for parents inside a task: levels 3 .. 3 + kMaxLocal - 1.
 constexpr int kMaxLocal = kPlanCandidates;
 
+// Lane geometry for blocks of B words.  A lane reads 16 bytes (instances 2r
+// and 2r + 1) of each block, so a block takes LPB = B / 2 lanes and a wave
+// has G = 64 / LPB lane groups; each lane group works through 8 consecutive
+// executions (one level-1 node) per pass, so a pass is PASS = 8 G executions
+// and holds NG2 = G / 8 level-2 nodes.
+template <int B>
+struct Geo {
+  static constexpr int LPB = B / 2;
+  static constexpr int G = 64 / LPB;
+  static constexpr int PASS = 8 * G;
+  static constexpr int NG2 = G / 8;
+  static constexpr int LOG_PASS = B == 8 ? 7 : 8;
+  static_assert(B == 4 || B == 8, "block size");
+  static_assert(PASS == 1 << LOG_PASS, "pass size");
+};
+
 template <int WIDTH>
 struct Ctx {
   static constexpr int K = Family<WIDTH>::K;
   const uint64_t* __restrict__ ent;
   uint64_t N;
-  uint32_t j;  // task size 128 * 8^j executions
+  uint32_t j;  // task size PASS * 8^j executions
   uint64_t acc_base;
   uint64_t* gacc;
   uint32_t* gcnt;
@@ -490,15 +512,15 @@ __device__ __forceinline__ uint64_t acc_index(uint64_t N, uint32_t j, int l, uin
 }
 
 // Fold one complete node of level l (index n within the string), held by
-// lanes 0..3 (instances 2r, 2r+1 of every tree), into the tree above it.
-// Called by the whole wave; all control flow is wave-uniform.
-template <int WIDTH>
+// lanes 0 .. LPB-1 (instances 2r, 2r+1 of every tree), into the tree above
+// it.  Called by the whole wave; all control flow is wave-uniform.
+template <int WIDTH, int B>
 __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], uint64_t v1[], uint64_t F[],
-                        uint64_t (*lacc)[Family<WIDTH>::K][kBlock]) {
+                        uint64_t (*lacc)[Family<WIDTH>::K][B]) {
   constexpr int K = Family<WIDTH>::K;
-  using Ly = Layout<WIDTH>;
+  using Ly = Layout<WIDTH, B>;
   const int lane = threadIdx.x;
-  const bool owner = lane < 4;
+  const bool owner = lane < Geo<B>::LPB;
   const int j0 = 2 * lane, j1 = 2 * lane + 1;
   for (;;) {
     const uint64_t parent = n >> 3;
@@ -508,7 +530,7 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
       if (owner) {
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + l) * (kFan - 1) + pos) * kBlock;
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + l) * (kFan - 1) + pos) * B;
           F[t] = nh_acc(F[t], v0[t], kf[j0]);
           F[t] = nh_acc(F[t], v1[t], kf[j1]);
         }
@@ -583,43 +605,47 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
   }
 }
 
-// The last pass of a string, nv < 128 executions starting at execution p:
-// execution p + 16e + q goes to lane group q (e = 0 .. ceil(nv/16) - 1), so
-// the executions spread over all 16 lane groups (a lane does at most
-// ceil(nv/16) of them instead of up to 8).  Execution 16e + q is child
-// q mod 8 of level-1 node 2e + q/8; the 8 children of a node sit in the
-// lane groups of one half-row and are summed across lanes.  Complete level-1
-// nodes either join level-2 node p/64 (when nv >= 64 and node < 8) or are
-// leftover items of level 1; the executions of the incomplete level-1 node
-// are leftover items of level 0.  Called by the whole wave (nv uniform).
-template <int WIDTH>
+// The last pass of a string, nv < PASS executions starting at execution p:
+// execution p + G e + q goes to lane group q (e = 0 .. ceil(nv/G) - 1), so
+// the executions spread over all G lane groups (a lane does at most
+// ceil(nv/G) of them instead of up to 8).  Execution G e + q is child q mod 8
+// of level-1 node NG2 e + q/8; the 8 children of a node sit in 8 adjacent
+// lane groups and are summed across lanes.  Complete level-1 nodes either
+// join a complete level-2 node (its children arrive over 8/NG2 consecutive
+// steps, from the lane groups q = 0, 8, 16, ...) or are leftover items of
+// level 1; the executions of the incomplete level-1 node are leftover items
+// of level 0.  Called by the whole wave (nv uniform).
+template <int WIDTH, int B>
 __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
-                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][kBlock]) {
-  using Ly = Layout<WIDTH>;
+                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B]) {
+  using Ly = Layout<WIDTH, B>;
+  using Gm = Geo<B>;
   constexpr int K = Family<WIDTH>::K;
   constexpr uint64_t XB = Ly::exec_bytes;
+  constexpr uint32_t kPer2 = 8 / Gm::NG2;  // steps that feed one level-2 node
   const int lane = threadIdx.x;
-  const int q = lane >> 2, r = lane & 3;
+  const int q = lane / Gm::LPB, r = lane % Gm::LPB;
   const int h = q >> 3, pos0 = q & 7;
-  const uint32_t full1 = nv / 8;  // complete level-1 nodes of the pass
-  const bool full2 = nv >= 64;    // level-2 node p/64 complete
-  uint64_t k0[K];                 // level-0 key of this lane's child position
+  const uint32_t full1 = nv / 8;   // complete level-1 nodes of the pass
+  const uint32_t full2 = nv / 64;  // complete level-2 nodes (fewer than NG2)
+  uint64_t k0[K];                  // level-0 key of this lane's child position
 #pragma unroll
   for (int t = 0; t < K; ++t) k0[t] = pos0 < kFan - 1 ? c.ent[Ly::tree + (t * kLevels) * (kFan - 1) + pos0] : 0;
-  uint64_t s0[K], s1[K];  // terms of level-2 node p/64 (lanes of pos0 == 0)
+  uint64_t s0[K], s1[K];  // terms of the current level-2 node (lanes of pos0 == 0)
 #pragma unroll
   for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
-  const uint32_t steps = (nv + 15) / 16;
+  const uint32_t steps = (nv + Gm::G - 1) / Gm::G;
   for (uint32_t e = 0; e < steps; ++e) {
-    const uint32_t i = 16 * e + (uint32_t)q;  // execution within the pass
-    const uint32_t m = 2 * e + (uint32_t)h;   // its level-1 node
+    const uint32_t i = Gm::G * e + (uint32_t)q;  // execution within the pass
+    const uint32_t m = Gm::NG2 * e + (uint32_t)h;  // its level-1 node
+    const uint32_t g = e / kPer2;                // that node's level-2 parent (uniform)
     const bool node_full = m < full1;
     uint64_t t0[K], t1[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) t0[t] = t1[t] = 0;
     if (i < nv) {
       uint64_t z0[K], z1[K];
-      ehc2<WIDTH>(str + (p + i) * XB + 16 * r, uniform_keys(c.ent + Ly::ehc), z0, z1);
+      ehc2<WIDTH, B>(str + (p + i) * XB + 16 * r, uniform_keys(c.ent + Ly::ehc), z0, z1);
       if (node_full) {
 #pragma unroll
         for (int t = 0; t < K; ++t) {
@@ -630,29 +656,28 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
         // child of the incomplete level-1 node: leftover item (0, pos0)
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + pos0) * kBlock;
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + pos0) * B;
           F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
           F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
         }
       }
     }
-    // sum the 8 children of each level-1 node (lane bits 2..4 = q mod 8)
+    // sum the 8 children of each level-1 node (q mod 8 = lane bits above r)
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      t0[t] += shfl_xor64(t0[t], 4);
-      t1[t] += shfl_xor64(t1[t], 4);
-      t0[t] += shfl_xor64(t0[t], 8);
-      t1[t] += shfl_xor64(t1[t], 8);
-      t0[t] += shfl_xor64(t0[t], 16);
-      t1[t] += shfl_xor64(t1[t], 16);
+#pragma unroll
+      for (int msk = Gm::LPB; msk < 8 * Gm::LPB; msk <<= 1) {
+        t0[t] += shfl_xor64(t0[t], msk);
+        t1[t] += shfl_xor64(t1[t], msk);
+      }
     }
     if (pos0 == 0 && node_full) {
-      if (full2 && m < (uint32_t)kFan) {
-        // child m of level-2 node p/64
+      if (g < full2) {
+        // child m mod 8 of level-2 node g
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          if (m < (uint32_t)kFan - 1) {
-            const uint64_t key = c.ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + m];
+          if ((m & 7) < (uint32_t)kFan - 1) {
+            const uint64_t key = c.ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + (m & 7)];
             s0[t] = nh_acc(s0[t], t0[t], key);
             s1[t] = nh_acc(s1[t], t1[t], key);
           } else {
@@ -664,29 +689,35 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
         // complete level-1 node with an incomplete parent: leftover (1, m mod 8)
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + (m & 7)) * kBlock;
+          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + (m & 7)) * B;
           F[t] = nh_acc(F[t], t0[t], kf[2 * r]);
           F[t] = nh_acc(F[t], t1[t], kf[2 * r + 1]);
         }
       }
     }
-  }
-  if (full2) {
-    // even children sit in lanes 0..3, odd ones in lanes 32..35
+    if (e % kPer2 == kPer2 - 1 && g < full2) {
+      // all children of level-2 node g are in: sum the lane groups q = 8h
+      // into lanes 0 .. LPB-1 and fold it up
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-      s0[t] += shfl64(s0[t], (lane & 3) + 32);
-      s1[t] += shfl64(s1[t], (lane & 3) + 32);
+      for (int t = 0; t < K; ++t) {
+#pragma unroll
+        for (int msk = 8 * Gm::LPB; msk < 64; msk <<= 1) {
+          s0[t] += shfl_xor64(s0[t], msk);
+          s1[t] += shfl_xor64(s1[t], msk);
+        }
+      }
+      fold_up<WIDTH, B>(c, 2, (p >> 6) + g, s0, s1, F, lacc);
+#pragma unroll
+      for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
     }
-    fold_up<WIDTH>(c, 2, p >> 6, s0, s1, F, lacc);
   }
 }
 
 // One tail-only string: its tail words hashed with the Toeplitz keys of
 // §6.1 plus the length term, by one lane.
-template <int WIDTH>
+template <int WIDTH, int B>
 __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
-  using Ly = Layout<WIDTH>;
+  using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
   const uint64_t* __restrict__ ent = a.ent;
   const uint64_t L = a.lengths[s];
@@ -731,7 +762,7 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
 // from a device counter.  A separate kernel: inside the hashing kernel this
 // code cost the full passes 3-10 % (register allocation of the whole
 // kernel), while a launch costs a few microseconds.
-template <int WIDTH>
+template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
   const int lane = threadIdx.x;
   const uint32_t ntiny = uniform(a.ctl[kCtlTiny]);
@@ -747,27 +778,28 @@ __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
     k = uniform(k);
     if (k >= nchunks) return;
     const uint32_t idx = k * kTinyChunk + (uint32_t)lane;
-    if (idx < ntiny) tiny_one<WIDTH>(a, a.tiny_list[idx]);
+    if (idx < ntiny) tiny_one<WIDTH, B>(a, a.tiny_list[idx]);
   }
 }
 
-template <int WIDTH>
+template <int WIDTH, int B>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void hash_main_kernel(MainArgs a) {
   using Fm = Family<WIDTH>;
-  using Ly = Layout<WIDTH>;
+  using Ly = Layout<WIDTH, B>;
+  using Gm = Geo<B>;
   constexpr int K = Fm::K;
   constexpr uint64_t XB = Ly::exec_bytes;
-  __shared__ uint64_t lacc[kMaxLocal][K][kBlock];
+  __shared__ uint64_t lacc[kMaxLocal][K][B];
 
   const int lane = threadIdx.x;
-  const int q = lane >> 2, r = lane & 3;
+  const int q = lane / Gm::LPB, r = lane % Gm::LPB;
   const uint32_t nb = uniform(a.ctl[kCtlBuckets]);
   const uint32_t jlev = uniform(a.ctl[kCtlLevel]);
-  const uint64_t texec = 128ull << (3 * jlev);
+  const uint64_t texec = (uint64_t)Gm::PASS << (3 * jlev);
   const uint64_t* __restrict__ ent = a.ent;
 
-  // each owner lane (0..3) only ever touches its own two instances' slots
-  if (lane < 4) {
+  // each owner lane (0 .. LPB-1) only ever touches its own two instances' slots
+  if (lane < Gm::LPB) {
     for (int li = 0; li < kMaxLocal; ++li)
 #pragma unroll
       for (int t = 0; t < K; ++t) lacc[li][t][2 * lane] = lacc[li][t][2 * lane + 1] = 0;
@@ -839,8 +871,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = 0;
 
-    if (N < 128) {
-      // a string of fewer than 128 executions (one task): its tail words
+    if (N < Gm::PASS) {
+      // a string of fewer than PASS executions (one task): its tail words
       // are loaded together with its data, then one partial pass
       const uint64_t tb = N * XB;
       const uint64_t rem = L - tb;
@@ -859,7 +891,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           }
         }
       }
-      if (N) partial_pass<WIDTH>(c, str, 0, (uint32_t)N, F, lacc);
+      if (N) partial_pass<WIDTH, B>(c, str, 0, (uint32_t)N, F, lacc);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
@@ -875,10 +907,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     } else {
       const uint64_t g0 = tau * texec;
       const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
-      for (uint64_t p = g0; p < g1; p += 128) {
-        if (N - p < 128) {
+      for (uint64_t p = g0; p < g1; p += Gm::PASS) {
+        if (N - p < Gm::PASS) {
           // the string's last, partial pass
-          partial_pass<WIDTH>(c, str, p, (uint32_t)(N - p), F, lacc);
+          partial_pass<WIDTH, B>(c, str, p, (uint32_t)(N - p), F, lacc);
           break;
         }
         // full pass: lane group q takes the 8 consecutive executions
@@ -889,7 +921,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
         for (int e = 0; e < 8; ++e) {
           uint64_t z0[K], z1[K];
-          ehc2<WIDTH>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
+          ehc2<WIDTH, B>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
           // level 0 of every tree: child e of this lane's level-1 node
           if (e < kFan - 1) {
 #pragma unroll
@@ -921,26 +953,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             t0 = a0[t];
             t1 = a1[t];
           }
-          t0 += shfl_xor64(t0, 4);
-          t1 += shfl_xor64(t1, 4);
-          t0 += shfl_xor64(t0, 8);
-          t1 += shfl_xor64(t1, 8);
-          t0 += shfl_xor64(t0, 16);
-          t1 += shfl_xor64(t1, 16);
+#pragma unroll
+          for (int msk = Gm::LPB; msk < 8 * Gm::LPB; msk <<= 1) {
+            t0 += shfl_xor64(t0, msk);
+            t1 += shfl_xor64(t1, msk);
+          }
           n0[t] = t0;
           n1[t] = t1;
         }
-        // lanes 0..3 hold level-2 node A (executions p .. p+63), lanes 32..35
-        // node B (p+64 .. p+127)
-        const uint64_t nA = p >> 6;
-        uint64_t b0[K], b1[K];
+        // lanes 8 g LPB + r (lane group q = 8g) hold level-2 node p/64 + g;
+        // each is brought to lanes 0 .. LPB-1 and folded up (fold_up may
+        // overwrite its argument arrays, so it gets copies)
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-          b0[t] = shfl64(n0[t], (lane & 3) + 32);
-          b1[t] = shfl64(n1[t], (lane & 3) + 32);
+        for (int g = 0; g < Gm::NG2; ++g) {
+          uint64_t b0[K], b1[K];
+#pragma unroll
+          for (int t = 0; t < K; ++t) {
+            b0[t] = g ? shfl64(n0[t], r + 8 * Gm::LPB * g) : n0[t];
+            b1[t] = g ? shfl64(n1[t], r + 8 * Gm::LPB * g) : n1[t];
+          }
+          fold_up<WIDTH, B>(c, 2, (p >> 6) + g, b0, b1, F, lacc);
         }
-        fold_up<WIDTH>(c, 2, nA, n0, n1, F, lacc);
-        fold_up<WIDTH>(c, 2, nA + 1, b0, b1, F, lacc);
       }
 
       if (tau == ntask - 1) {
@@ -1039,73 +1072,74 @@ __global__ __launch_bounds__(kProbeThreads) void read_probe_kernel(const uint4* 
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 
-template <int WIDTH>
-static const void* main_fn() {
-  return reinterpret_cast<const void*>(&hash_main_kernel<WIDTH>);
+// Instantiates fn<W, B> for the runtime (width, block) pair.
+#define HTH_DISPATCH(width, block, ...)                              \
+  do {                                                               \
+    if ((block) == 8) {                                              \
+      switch (width) {                                               \
+        case 16: { constexpr int W = 16, Bk = 8; __VA_ARGS__; } break; \
+        case 24: { constexpr int W = 24, Bk = 8; __VA_ARGS__; } break; \
+        case 32: { constexpr int W = 32, Bk = 8; __VA_ARGS__; } break; \
+        case 40: { constexpr int W = 40, Bk = 8; __VA_ARGS__; } break; \
+      }                                                              \
+    } else if ((block) == 4) {                                       \
+      switch (width) {                                               \
+        case 16: { constexpr int W = 16, Bk = 4; __VA_ARGS__; } break; \
+        case 24: { constexpr int W = 24, Bk = 4; __VA_ARGS__; } break; \
+        case 32: { constexpr int W = 32, Bk = 4; __VA_ARGS__; } break; \
+        case 40: { constexpr int W = 40, Bk = 4; __VA_ARGS__; } break; \
+      }                                                              \
+    }                                                                \
+  } while (0)
+
+const void* main_kernel_fn(uint32_t width, uint32_t block) {
+  const void* f = nullptr;
+  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&hash_main_kernel<W, Bk>));
+  return f;
 }
 
-const void* main_kernel_fn(uint32_t width) {
-  switch (width) {
-    case 16: return main_fn<16>();
-    case 24: return main_fn<24>();
-    case 32: return main_fn<32>();
-    case 40: return main_fn<40>();
-  }
-  return nullptr;
+uint32_t exec_bytes_of(uint32_t width, uint32_t block) {
+  uint32_t x = 0;
+  HTH_DISPATCH(width, block, x = Layout<W, Bk>::exec_bytes);
+  return x;
 }
 
-uint32_t exec_bytes_of(uint32_t width) {
-  switch (width) {
-    case 16: return Layout<16>::exec_bytes;
-    case 24: return Layout<24>::exec_bytes;
-    case 32: return Layout<32>::exec_bytes;
-    case 40: return Layout<40>::exec_bytes;
-  }
-  return 0;
-}
+uint32_t pass_log2_of(uint32_t block) { return block == 4 ? Geo<4>::LOG_PASS : Geo<8>::LOG_PASS; }
 
-int64_t entropy_offset_of(uint32_t width) { return width_offset((int)width); }
-uint64_t entropy_words_total() { return kEntropyWords; }
+int64_t entropy_offset_of(uint32_t width, uint32_t block) {
+  return block == 4 ? width_offset<4>((int)width) : block == 8 ? width_offset<8>((int)width) : -1;
+}
+uint64_t entropy_words_total(uint32_t block) {
+  return block == 4 ? entropy_words<4>() : block == 8 ? entropy_words<8>() : 0;
+}
 
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const uint32_t nblocks = (uint32_t)((p.count + kPlanBlock - 1) / kPlanBlock);
   if (nblocks == 1) {
     hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
-                       p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
+                       p.pass_log2, p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
                        p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.block_sums, p.ctl);
+                     p.exec_bytes, p.pass_log2, p.block_sums, p.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
+                     p.exec_bytes, p.pass_log2, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
                      p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_main(uint32_t width, const MainArgs& a, uint32_t grid, hipStream_t stream) {
+hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream) {
   // the hashing kernel, then the tail-only strings
-  switch (width) {
-    case 16:
-      hipLaunchKernelGGL(hash_main_kernel<16>, dim3(grid), dim3(64), 0, stream, a);
-      hipLaunchKernelGGL(tiny_kernel<16>, dim3(grid), dim3(64), 0, stream, a);
-      break;
-    case 24:
-      hipLaunchKernelGGL(hash_main_kernel<24>, dim3(grid), dim3(64), 0, stream, a);
-      hipLaunchKernelGGL(tiny_kernel<24>, dim3(grid), dim3(64), 0, stream, a);
-      break;
-    case 32:
-      hipLaunchKernelGGL(hash_main_kernel<32>, dim3(grid), dim3(64), 0, stream, a);
-      hipLaunchKernelGGL(tiny_kernel<32>, dim3(grid), dim3(64), 0, stream, a);
-      break;
-    case 40:
-      hipLaunchKernelGGL(hash_main_kernel<40>, dim3(grid), dim3(64), 0, stream, a);
-      hipLaunchKernelGGL(tiny_kernel<40>, dim3(grid), dim3(64), 0, stream, a);
-      break;
-    default: return hipErrorInvalidValue;
-  }
+  bool known = false;
+  HTH_DISPATCH(width, block, {
+    hipLaunchKernelGGL((hash_main_kernel<W, Bk>), dim3(grid), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((tiny_kernel<W, Bk>), dim3(grid), dim3(64), 0, stream, a);
+    known = true;
+  });
+  if (!known) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

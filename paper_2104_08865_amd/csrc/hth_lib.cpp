@@ -68,7 +68,7 @@ constexpr uint32_t kDefaultWavesPerCU = 8;
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 Tuning g_tune[4];
-std::map<std::pair<int, int>, uint32_t> g_grid;  // (device, width index) -> persistent grid
+std::map<std::pair<int, int>, uint32_t> g_grid;  // (device, width index + 4 for b = 4) -> persistent grid
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -152,13 +152,14 @@ hth_status get_ws(uint64_t count, hipStream_t stream, Workspace** out) {
   return HTH_OK;
 }
 
-hth_status grid_for(uint32_t width, uint32_t* grid) {
+hth_status grid_for(uint32_t width, uint32_t block, uint32_t* grid) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   std::lock_guard<std::mutex> lk(g_mu);
   const int wi = width_index(width);
-  auto it = g_grid.find({dev, wi});
+  const int key = wi + (block == 4 ? 4 : 0);
+  auto it = g_grid.find({dev, key});
   if (it != g_grid.end()) {
     *grid = it->second;
     return HTH_OK;
@@ -166,13 +167,13 @@ hth_status grid_for(uint32_t width, uint32_t* grid) {
   int cus = 0, per_cu = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "device attribute");
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::main_kernel_fn(width), 64, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::main_kernel_fn(width, block), 64, 0);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   uint32_t wpc = per_cu > 0 ? (uint32_t)per_cu : 1;
   const uint32_t want = g_tune[wi].waves_per_cu ? g_tune[wi].waves_per_cu : kDefaultWavesPerCU;
   if (want < wpc) wpc = want;
   *grid = (uint32_t)cus * wpc;
-  g_grid[{dev, wi}] = *grid;
+  g_grid[{dev, key}] = *grid;
   return HTH_OK;
 }
 
@@ -206,8 +207,9 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
                          hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves) {
+  const uint32_t block = seed->block;
   uint32_t grid = 0;
-  hth_status st = grid_for(out_width, &grid);
+  hth_status st = grid_for(out_width, block, &grid);
   if (st != HTH_OK) return st;
   if (max_waves && max_waves < grid) grid = (uint32_t)max_waves;
   Tuning tune;
@@ -218,7 +220,8 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   hth::PlanArgs p{};
   p.lengths = lengths;
   p.count = count;
-  p.exec_bytes = hth::exec_bytes_of(out_width);
+  p.exec_bytes = hth::exec_bytes_of(out_width, block);
+  p.pass_log2 = hth::pass_log2_of(block);
   p.block_sums = w.block_sums;
   p.cap_tasks = w.cap_tasks;
   p.cap_accs = w.cap_accs;
@@ -239,7 +242,7 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.offsets = offsets;
   a.lengths = lengths;
   a.out = out;
-  a.ent = seed->d_words + hth::entropy_offset_of(out_width);
+  a.ent = seed->d_words + hth::entropy_offset_of(out_width, block);
   a.task_string = w.task_string;
   a.task_start = w.task_start;
   a.acc_start = w.acc_start;
@@ -251,15 +254,16 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.tiny_list = w.tiny_list;
   a.ctl = w.ctl;
   if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
-  e = hth::launch_main(out_width, a, grid, stream);
+  e = hth::launch_main(out_width, block, a, grid, stream);
   if (e != hipSuccess) return hip_fail(e, "main launch");
   if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;
 }
 
-uint64_t task_bound(uint64_t len, uint32_t out_width) {
-  const uint64_t n = len / hth::exec_bytes_of(out_width);
-  return n ? (n + 127) / 128 : 1;
+uint64_t task_bound(uint64_t len, uint32_t out_width, uint32_t block) {
+  const uint64_t n = len / hth::exec_bytes_of(out_width, block);
+  const uint64_t pass = 1ull << hth::pass_log2_of(block);
+  return n ? (n + pass - 1) / pass : 1;
 }
 
 // Synchronise and read a workspace's planner status word.
@@ -282,17 +286,23 @@ extern "C" {
 
 const char* hth_last_error(void) { return g_err.c_str(); }
 
-size_t hth_entropy_words(void) { return (size_t)hth::entropy_words_total(); }
+size_t hth_entropy_words(void) { return (size_t)hth::entropy_words_total(8); }
 
-hth_status hth_seed_from_entropy(const uint64_t* words, size_t n_words, hth_seed** out, hipStream_t stream) {
+size_t hth_entropy_words_b(uint32_t block_words) { return (size_t)hth::entropy_words_total(block_words); }
+
+hth_status hth_seed_from_entropy_b(const uint64_t* words, size_t n_words, uint32_t block_words, hth_seed** out,
+                                   hipStream_t stream) {
   if (!out) return fail(HTH_E_INVALID, "hth_seed_from_entropy: out is null");
   *out = nullptr;
+  if (block_words != 4 && block_words != 8)
+    return fail(HTH_E_INVALID, "hth_seed_from_entropy: block_words %u is not 4 or 8", block_words);
   if (!words) return fail(HTH_E_INVALID, "hth_seed_from_entropy: words is null");
-  if (n_words != hth_entropy_words())
+  if (n_words != hth_entropy_words_b(block_words))
     return fail(HTH_E_INVALID, "hth_seed_from_entropy: n_words is %zu, expected %zu", n_words,
-                hth_entropy_words());
+                hth_entropy_words_b(block_words));
   hth_seed* s = new (std::nothrow) hth_seed;
   if (!s) return fail(HTH_E_OOM, "hth_seed_from_entropy: host allocation");
+  s->block = block_words;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) {
     delete s;
@@ -315,12 +325,24 @@ hth_status hth_seed_from_entropy(const uint64_t* words, size_t n_words, hth_seed
   return HTH_OK;
 }
 
-hth_status hth_expand_seed(uint64_t user_seed, hth_seed** out, hipStream_t stream) {
-  if (!out) return fail(HTH_E_INVALID, "hth_expand_seed: out is null");
-  std::vector<uint64_t> w(hth_entropy_words());
-  splitmix64_fill(user_seed, w.data(), w.size());
-  return hth_seed_from_entropy(w.data(), w.size(), out, stream);
+hth_status hth_seed_from_entropy(const uint64_t* words, size_t n_words, hth_seed** out, hipStream_t stream) {
+  return hth_seed_from_entropy_b(words, n_words, 8, out, stream);
 }
+
+hth_status hth_expand_seed_b(uint64_t user_seed, uint32_t block_words, hth_seed** out, hipStream_t stream) {
+  if (!out) return fail(HTH_E_INVALID, "hth_expand_seed: out is null");
+  if (block_words != 4 && block_words != 8)
+    return fail(HTH_E_INVALID, "hth_expand_seed: block_words %u is not 4 or 8", block_words);
+  std::vector<uint64_t> w(hth_entropy_words_b(block_words));
+  splitmix64_fill(user_seed, w.data(), w.size());
+  return hth_seed_from_entropy_b(w.data(), w.size(), block_words, out, stream);
+}
+
+hth_status hth_expand_seed(uint64_t user_seed, hth_seed** out, hipStream_t stream) {
+  return hth_expand_seed_b(user_seed, 8, out, stream);
+}
+
+uint32_t hth_seed_block_words(const hth_seed* seed) { return seed ? seed->block : 0; }
 
 hth_status hth_seed_entropy(const hth_seed* seed, uint64_t* host_words, size_t n_words) {
   if (!seed || !host_words) return fail(HTH_E_INVALID, "hth_seed_entropy: null pointer");
@@ -354,7 +376,7 @@ hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t mi
   g_tune[wi].min_j = min_task_level;
   g_tune[wi].max_j = max_task_level;
   for (auto it = g_grid.begin(); it != g_grid.end();) {
-    if (it->first.second == wi) it = g_grid.erase(it);
+    if (it->first.second % 4 == wi) it = g_grid.erase(it);
     else ++it;
   }
   return HTH_OK;
@@ -386,7 +408,7 @@ hth_status hth_batch_graph_create(const hth_seed* seed, const uint8_t* bytes, co
   if (st != HTH_OK) return st;
   if (count == 0) return fail(HTH_E_INVALID, "hth_batch_graph_create: count is 0");
   uint32_t grid = 0;
-  st = grid_for(out_width, &grid);  // fills the cache outside the capture
+  st = grid_for(out_width, seed->block, &grid);  // fills the cache outside the capture
   if (st != HTH_OK) return st;
   hth_batch_graph* g = new (std::nothrow) hth_batch_graph;
   if (!g) return fail(HTH_E_OOM, "hth_batch_graph_create: host allocation");

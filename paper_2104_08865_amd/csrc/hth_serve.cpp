@@ -210,7 +210,7 @@ bool launch_batch(hth_server* s, uint32_t si) {
   uint64_t fillw[kWidths] = {}, waves[kWidths] = {};
   for (const Request& r : sl.reqs) {
     const int w = widx(r.width);
-    waves[w] += task_bound(r.len, r.width);
+    waves[w] += task_bound(r.len, r.width, s->seed->block);
     sl.h_meta[meta_at[w] + fillw[w]] = r.dev_pos % s->dev.cap;
     sl.h_meta[meta_at[w] + n[w] + fillw[w]] = r.len;
     ++fillw[w];

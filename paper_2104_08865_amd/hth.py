@@ -29,7 +29,8 @@ SYMBOLS = (
     "hth_batch_check", "hth_set_tuning", "hth_batch_graph_create", "hth_batch_graph_launch",
     "hth_batch_graph_check", "hth_batch_graph_free", "hth_serve_create", "hth_serve_submit",
     "hth_serve_poll", "hth_serve_wait", "hth_serve_wait_many", "hth_serve_replay", "hth_serve_stats",
-    "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause", "hth_read_probe",
+    "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause", "hth_read_probe", "hth_entropy_words_b",
+    "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words",
 )
 
 
@@ -97,8 +98,14 @@ def lib():
         L.hth_serve_destroy.argtypes = [vp]
         L.hth_serve_pause.argtypes = [vp, ctypes.c_int32]
         L.hth_read_probe.argtypes = [vp, u64, vp, u32, vp]
+        L.hth_entropy_words_b.argtypes = [u32]
+        L.hth_expand_seed_b.argtypes = [u64, u32, ctypes.POINTER(vp), vp]
+        L.hth_seed_from_entropy_b.argtypes = [vp, ctypes.c_size_t, u32, ctypes.POINTER(vp), vp]
+        L.hth_seed_block_words.argtypes = [vp]
         for name in SYMBOLS[2:]:
             getattr(L, name).restype = ctypes.c_int32
+        L.hth_entropy_words_b.restype = ctypes.c_size_t
+        L.hth_seed_block_words.restype = ctypes.c_uint32
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
                      "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning",
                      "hth_batch_graph_create", "hth_batch_graph_launch", "hth_batch_graph_check",
@@ -119,8 +126,9 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def entropy_words():
-    return int(lib().hth_entropy_words())
+def entropy_words(block_words=8):
+    """Entropy words of a seed of the family with `block_words` (8 or 4)."""
+    return int(lib().hth_entropy_words_b(block_words))
 
 
 class Seed:
@@ -133,8 +141,12 @@ class Seed:
     def handle(self):
         return self._h
 
+    @property
+    def block_words(self):
+        return int(lib().hth_seed_block_words(self._h))
+
     def entropy(self):
-        out = np.zeros(entropy_words(), dtype=np.uint64)
+        out = np.zeros(entropy_words(self.block_words), dtype=np.uint64)
         _check(lib().hth_seed_entropy(self._h, out.ctypes.data, out.size))
         return out
 
@@ -150,16 +162,19 @@ class Seed:
             pass
 
 
-def expand_seed(user_seed, stream=None):
+def expand_seed(user_seed, stream=None, block_words=8):
+    """splitmix64 expansion of a user seed into the family with
+    `block_words` words per block (8, the default, or 4)."""
     h = ctypes.c_void_p()
-    _check(lib().hth_expand_seed(ctypes.c_uint64(user_seed & (2**64 - 1)), ctypes.byref(h), _stream(stream)))
+    _check(lib().hth_expand_seed_b(ctypes.c_uint64(user_seed & (2**64 - 1)), block_words, ctypes.byref(h),
+                                   _stream(stream)))
     return Seed(h)
 
 
-def seed_from_entropy(words, stream=None):
+def seed_from_entropy(words, stream=None, block_words=8):
     w = np.ascontiguousarray(words, dtype=np.uint64)
     h = ctypes.c_void_p()
-    _check(lib().hth_seed_from_entropy(w.ctypes.data, w.size, ctypes.byref(h), _stream(stream)))
+    _check(lib().hth_seed_from_entropy_b(w.ctypes.data, w.size, block_words, ctypes.byref(h), _stream(stream)))
     # the upload reads host memory owned by the library; nothing to keep here
     return Seed(h)
 

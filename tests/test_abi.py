@@ -100,3 +100,20 @@ def test_serve_config_rejections(lib):
     t = ctypes.c_uint64()
     assert lib.hth_serve_submit(None, None, 0, 16, ctypes.byref(t)) == hth.HTH_E_INVALID
     assert lib.hth_serve_destroy(None) == hth.HTH_OK
+
+
+def test_block_size_entry_points(lib):
+    """The 256-bit block family's sizes and argument checks (no device use)."""
+    from paper_2104_08865_amd import hth
+    assert lib.hth_entropy_words_b(8) == lib.hth_entropy_words()
+    # per width [e*w][k*140][k*140*4][4*d*w + k - 1][k], widths 16, 24, 32, 40
+    shapes = {16: (6, 7, 2), 24: (7, 9, 3), 32: (7, 10, 4), 40: (5, 9, 5)}
+    assert lib.hth_entropy_words_b(4) == sum(e * 3 + k * 140 * 5 + 4 * d * 3 + k - 1 + k
+                                             for d, e, k in shapes.values())
+    assert lib.hth_entropy_words_b(5) == 0
+    h = ctypes.c_void_p()
+    assert lib.hth_expand_seed_b(1, 5, ctypes.byref(h), None) == hth.HTH_E_INVALID
+    words = (ctypes.c_uint64 * 10229)()
+    assert lib.hth_seed_from_entropy_b(words, 10229, 8, ctypes.byref(h), None) == hth.HTH_E_INVALID
+    assert lib.hth_seed_from_entropy_b(words, 10229, 3, ctypes.byref(h), None) == hth.HTH_E_INVALID
+    assert lib.hth_seed_block_words(None) == 0
