@@ -203,6 +203,54 @@ hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t mi
                           uint32_t max_task_level);
 
 /* ------------------------------------------------------------------------ */
+/* Streaming: one string hashed from pieces appended over time.  The value  */
+/* equals hth_hash_batch's for the concatenation of all pieces.  The state  */
+/* is the tree stack of Eq. (3) (at most 7 pending items of k x b words per */
+/* level) plus the bytes of the execution being filled, kept on the device; */
+/* it can be saved to host memory and loaded into another stream (resume).  */
+/* A stream object is used by one thread at a time.                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hth_stream hth_stream;
+
+/* Create an empty stream for `seed` (its family) and out_width.  Allocates
+   its device state (about 100 KB) and a planning workspace; synchronous.
+   The seed must outlive the stream.  Errors: HTH_E_INVALID (null pointer,
+   bad out_width, seed on another device), HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_stream **out);
+
+/* Append `len` bytes at device pointer `bytes` (any alignment), enqueued on
+   `stream`; the bytes must stay valid until that work completes.  Every
+   call on one hth_stream must be ordered (the same HIP stream, or
+   synchronised).  len == 0 is a no-op.  Errors: HTH_E_INVALID, HTH_E_HIP. */
+hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len, hipStream_t stream);
+
+/* Write the out_width-byte hash of everything appended so far to device
+   pointer `out` (enqueued on `stream`).  The stream is unchanged and can
+   take more updates.  Errors: HTH_E_INVALID, HTH_E_HIP. */
+hth_status hth_stream_final(hth_stream *st, uint8_t *out, hipStream_t stream);
+
+/* Back to the empty string (enqueued on `stream`). */
+hth_status hth_stream_reset(hth_stream *st, hipStream_t stream);
+
+/* Checkpoint: copy the state to host memory (synchronous on `stream`).
+   With host == NULL, *size receives the bytes needed; otherwise *size is
+   the buffer's size on entry (HTH_E_TOO_LARGE if too small) and the bytes
+   written on return. */
+hth_status hth_stream_save(hth_stream *st, void *host, size_t *size, hipStream_t stream);
+
+/* Resume: load a state saved from a stream of the same width and family
+   (synchronous on `stream`).  Errors: HTH_E_INVALID (not a saved state,
+   other width or family, truncated), HTH_E_HIP. */
+hth_status hth_stream_load(hth_stream *st, const void *host, size_t size, hipStream_t stream);
+
+/* Bytes appended so far (0 for null). */
+uint64_t hth_stream_length(const hth_stream *st);
+
+/* Free a stream (after its enqueued work completed).  Null is accepted. */
+hth_status hth_stream_free(hth_stream *st);
+
+/* ------------------------------------------------------------------------ */
 /* Serving loop.  Hash requests arrive one at a time as host bytes; a       */
 /* server admits them by device memory, gathers whatever has arrived into   */
 /* batches (continuous batching: a batch leaves as soon as a stream slot is */

@@ -55,9 +55,13 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 // using workspace `w` (events optional, recorded around the hashing kernel).
 // max_waves, when nonzero, caps the hashing kernel's grid: a caller that
 // knows the lengths on the host passes an upper bound of the batch's tasks.
+// roots, when non-null, selects root mode (every string a block of exactly
+// 8^L executions; its root node, kMaxK x 8 words, goes to roots[i]; out
+// is not written).
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
-                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0);
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0,
+                         uint64_t* roots = nullptr);
 
 // Upper bound of the tasks a string of `len` bytes can make (at the finest
 // task size) in the family with `block` words per block, for max_waves.

@@ -70,6 +70,7 @@ struct MainArgs {
   uint32_t* gcnt;  // [cap_accs], zero between launches
   const uint32_t* bucket_lead;
   const uint32_t* tiny_list;
+  uint64_t* roots;  // root mode only: [count][kMaxK * 8]
   uint32_t* ctl;
 };
 
@@ -85,5 +86,17 @@ hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
 // The hashing kernel, then the tail-only kernel, both with `grid` waves.
 hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
+
+// Streaming.  Root mode: every string is a block of exactly 8^L executions
+// whose root node (kMaxK x 8 words, [t][j]) goes to a.roots; no tail-only
+// strings.  The stack holds kLevels x 7 items of kMaxK x 8 words.
+constexpr int kStackWords = 20 * 7 * kMaxK * 8;
+hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
+                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
+                              hipStream_t stream);
+hipError_t launch_stream_final(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* stack,
+                               const uint32_t* counts, const uint8_t* tail, uint32_t tail_len, uint64_t total_len,
+                               uint8_t* out, hipStream_t stream);
 
 }  // namespace hth

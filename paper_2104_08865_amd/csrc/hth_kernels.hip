@@ -501,6 +501,7 @@ struct Ctx {
   uint64_t acc_base;
   uint64_t* gacc;
   uint32_t* gcnt;
+  uint64_t* roots;  // root mode: this string's root node, [K][8] words
 };
 
 // Offset of the accumulator of node `parent` at level l among one string's
@@ -514,7 +515,7 @@ __device__ __forceinline__ uint64_t acc_index(uint64_t N, uint32_t j, int l, uin
 // Fold one complete node of level l (index n within the string), held by
 // lanes 0 .. LPB-1 (instances 2r, 2r+1 of every tree), into the tree above
 // it.  Called by the whole wave; all control flow is wave-uniform.
-template <int WIDTH, int B>
+template <int WIDTH, int B, bool ROOTS>
 __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], uint64_t v1[], uint64_t F[],
                         uint64_t (*lacc)[Family<WIDTH>::K][B]) {
   constexpr int K = Family<WIDTH>::K;
@@ -528,11 +529,20 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
     if (parent >= nodes_at(c.N, l + 1)) {
       // the parent is incomplete: this node is a leftover item (l, pos)
       if (owner) {
+        if constexpr (ROOTS) {
+          // a block of 8^L executions: its only leftover is its root
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + l) * (kFan - 1) + pos) * B;
-          F[t] = nh_acc(F[t], v0[t], kf[j0]);
-          F[t] = nh_acc(F[t], v1[t], kf[j1]);
+          for (int t = 0; t < K; ++t) {
+            c.roots[t * kBlock + j0] = v0[t];
+            c.roots[t * kBlock + j1] = v1[t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < K; ++t) {
+            const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + l) * (kFan - 1) + pos) * B;
+            F[t] = nh_acc(F[t], v0[t], kf[j0]);
+            F[t] = nh_acc(F[t], v1[t], kf[j1]);
+          }
         }
       }
       return;
@@ -615,7 +625,7 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
 // steps, from the lane groups q = 0, 8, 16, ...) or are leftover items of
 // level 1; the executions of the incomplete level-1 node are leftover items
 // of level 0.  Called by the whole wave (nv uniform).
-template <int WIDTH, int B>
+template <int WIDTH, int B, bool ROOTS>
 __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
                              uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B]) {
   using Ly = Layout<WIDTH, B>;
@@ -652,6 +662,13 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
           t0[t] = pos0 < kFan - 1 ? nh_acc(0, z0[t], k0[t]) : z0[t];
           t1[t] = pos0 < kFan - 1 ? nh_acc(0, z1[t], k0[t]) : z1[t];
         }
+      } else if constexpr (ROOTS) {
+        // a block of one execution: the execution is the root
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          c.roots[t * kBlock + 2 * r] = z0[t];
+          c.roots[t * kBlock + 2 * r + 1] = z1[t];
+        }
       } else {
         // child of the incomplete level-1 node: leftover item (0, pos0)
 #pragma unroll
@@ -685,6 +702,13 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
             s1[t] += t1[t];
           }
         }
+      } else if constexpr (ROOTS) {
+        // a block of 8 executions: its level-1 node is the root
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          c.roots[t * kBlock + 2 * r] = t0[t];
+          c.roots[t * kBlock + 2 * r + 1] = t1[t];
+        }
       } else {
         // complete level-1 node with an incomplete parent: leftover (1, m mod 8)
 #pragma unroll
@@ -706,7 +730,7 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
           s1[t] += shfl_xor64(s1[t], msk);
         }
       }
-      fold_up<WIDTH, B>(c, 2, (p >> 6) + g, s0, s1, F, lacc);
+      fold_up<WIDTH, B, ROOTS>(c, 2, (p >> 6) + g, s0, s1, F, lacc);
 #pragma unroll
       for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
     }
@@ -782,7 +806,9 @@ __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
   }
 }
 
-template <int WIDTH, int B>
+// ROOTS: root mode (streaming): every string is a block of exactly 8^L
+// executions and its root node goes to a.roots instead of a hash to a.out.
+template <int WIDTH, int B, bool ROOTS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void hash_main_kernel(MainArgs a) {
   using Fm = Family<WIDTH>;
   using Ly = Layout<WIDTH, B>;
@@ -866,7 +892,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint64_t ntask = N ? (N + texec - 1) / texec : 1;
     const uint8_t* __restrict__ str = a.bytes + off;
 
-    Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)as : 0, a.gacc, a.gcnt};
+    Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)as : 0, a.gacc, a.gcnt,
+                 ROOTS ? a.roots + (uint64_t)s * (kMaxK * kBlock) : nullptr};
     uint64_t F[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = 0;
@@ -891,7 +918,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           }
         }
       }
-      if (N) partial_pass<WIDTH, B>(c, str, 0, (uint32_t)N, F, lacc);
+      if (N) partial_pass<WIDTH, B, ROOTS>(c, str, 0, (uint32_t)N, F, lacc);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
@@ -910,7 +937,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       for (uint64_t p = g0; p < g1; p += Gm::PASS) {
         if (N - p < Gm::PASS) {
           // the string's last, partial pass
-          partial_pass<WIDTH, B>(c, str, p, (uint32_t)(N - p), F, lacc);
+          partial_pass<WIDTH, B, ROOTS>(c, str, p, (uint32_t)(N - p), F, lacc);
           break;
         }
         // full pass: lane group q takes the 8 consecutive executions
@@ -972,7 +999,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             b0[t] = g ? shfl64(n0[t], r + 8 * Gm::LPB * g) : n0[t];
             b1[t] = g ? shfl64(n1[t], r + 8 * Gm::LPB * g) : n1[t];
           }
-          fold_up<WIDTH, B>(c, 2, (p >> 6) + g, b0, b1, F, lacc);
+          fold_up<WIDTH, B, ROOTS>(c, 2, (p >> 6) + g, b0, b1, F, lacc);
         }
       }
 
@@ -999,38 +1026,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       }
     }
 
+    if constexpr (!ROOTS) {
 #pragma unroll
-    for (int t = 0; t < K; ++t) F[t] = wave_sum64(F[t]);
+      for (int t = 0; t < K; ++t) F[t] = wave_sum64(F[t]);
 
-    uint8_t* o = a.out + (uint64_t)s * WIDTH;
-    if (ntask == 1) {
-      if (lane < K) {
-        uint64_t v = F[0];
-#pragma unroll
-        for (int t = 1; t < K; ++t)
-          if (lane == t) v = F[t];
-        __builtin_memcpy(o + 8 * lane, &v, 8);
-      }
-    } else {
-      uint64_t* sacc = a.sacc + (uint64_t)s * kMaxK;
-      if (lane < K) {
-        uint64_t v = F[0];
-#pragma unroll
-        for (int t = 1; t < K; ++t)
-          if (lane == t) v = F[t];
-        __hip_atomic_fetch_add(sacc + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      complete_atomics();
-      uint32_t old = 0;
-      if (lane == 0) old = __hip_atomic_fetch_add(a.sdone + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      old = uniform(old);
-      if (old == ntask - 1) {
-        // last task of the string: read and clear the sums and the counter
-        complete_atomics();
+      uint8_t* o = a.out + (uint64_t)s * WIDTH;
+      if (ntask == 1) {
         if (lane < K) {
-          uint64_t v = __hip_atomic_exchange(sacc + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          uint64_t v = F[0];
+#pragma unroll
+          for (int t = 1; t < K; ++t)
+            if (lane == t) v = F[t];
           __builtin_memcpy(o + 8 * lane, &v, 8);
-          __hip_atomic_store(a.sdone + s, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else {
+        uint64_t* sacc = a.sacc + (uint64_t)s * kMaxK;
+        if (lane < K) {
+          uint64_t v = F[0];
+#pragma unroll
+          for (int t = 1; t < K; ++t)
+            if (lane == t) v = F[t];
+          __hip_atomic_fetch_add(sacc + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        complete_atomics();
+        uint32_t old = 0;
+        if (lane == 0) old = __hip_atomic_fetch_add(a.sdone + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        old = uniform(old);
+        if (old == ntask - 1) {
+          // last task of the string: read and clear the sums and the counter
+          complete_atomics();
+          if (lane < K) {
+            uint64_t v = __hip_atomic_exchange(sacc + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_memcpy(o + 8 * lane, &v, 8);
+            __hip_atomic_store(a.sdone + s, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
       }
     }
@@ -1040,6 +1069,111 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     __builtin_amdgcn_wave_barrier();
   }
 
+}
+
+// ---------------------------------------------------------------------------
+// Streaming: the stack of Eq. (3) kept on the device between updates.
+// stack[l][i][t][j] (l < kLevels, i < 7, t < kMaxK, j < 8) holds the i-th
+// pending item of level l; counts[l] how many are pending.  One wave; lane
+// t * B + j owns word (t, j) of every item.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t* stack_at(uint64_t* stack, int l, int i) {
+  return stack + ((uint64_t)l * (kFan - 1) + i) * (kMaxK * kBlock);
+}
+
+// Push the roots of consecutive aligned blocks (root r at level levels[r])
+// in order: an item joins its level; the 8th completes the node
+// sum_{i<7} NH(item_i, S_tree[t][l][i]) + item_7, which is pushed one level up.
+template <int WIDTH, int B>
+__global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restrict__ ent,
+                                                         const uint64_t* __restrict__ roots,
+                                                         const uint32_t* __restrict__ levels, uint32_t nroots,
+                                                         uint64_t* __restrict__ stack, uint32_t* __restrict__ counts) {
+  using Ly = Layout<WIDTH, B>;
+  constexpr int K = Family<WIDTH>::K;
+  const int lane = threadIdx.x;
+  const bool mine = lane < K * B;
+  const int t = lane / B, j = lane % B, w = t * kBlock + j;
+  uint32_t cnt = lane < kLevels ? counts[lane] : 0;  // lane l holds counts[l]
+  for (uint32_t r = 0; r < nroots; ++r) {
+    int l = (int)levels[r];
+    uint64_t v = mine ? roots[(uint64_t)r * (kMaxK * kBlock) + w] : 0;
+    for (;;) {
+      const uint32_t c = (uint32_t)__shfl((int)cnt, l);
+      if (c < kFan - 1) {
+        if (mine) stack_at(stack, l, (int)c)[w] = v;
+        if (lane == l) cnt = c + 1;
+        break;
+      }
+      // the 8th child: close the node and carry it up
+      uint64_t node = v;
+      if (mine) {
+        for (int i = 0; i < kFan - 1; ++i)
+          node = nh_acc(node, stack_at(stack, l, i)[w], ent[Ly::tree + (t * kLevels + l) * (kFan - 1) + i]);
+      }
+      if (lane == l) cnt = 0;
+      v = node;
+      ++l;
+    }
+  }
+  if (lane < kLevels) counts[lane] = cnt;
+}
+
+// The hash of everything pushed so far plus the pending tail bytes: the
+// final NH over the pending items (§5.2), the Toeplitz tail (§6.1) and the
+// length term, as the batch kernel computes them.
+template <int WIDTH, int B>
+__global__ __launch_bounds__(64) void stream_final_kernel(const uint64_t* __restrict__ ent,
+                                                          const uint64_t* __restrict__ stack,
+                                                          const uint32_t* __restrict__ counts,
+                                                          const uint8_t* __restrict__ tail, uint32_t tail_len,
+                                                          uint64_t total_len, uint8_t* __restrict__ out) {
+  using Ly = Layout<WIDTH, B>;
+  constexpr int K = Family<WIDTH>::K;
+  const int lane = threadIdx.x;
+  uint64_t F[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) F[t] = 0;
+  // pending items: lane t * B + j hashes word (t, j) of each
+  if (lane < K * B) {
+    const int t = lane / B, j = lane % B;
+    for (int l = 0; l < kLevels; ++l) {
+      const uint32_t c = counts[l];
+      for (uint32_t i = 0; i < c; ++i) {
+        const uint64_t key = ent[Ly::fin + ((t * kLevels + l) * (kFan - 1) + i) * B + j];
+        const uint64_t v = nh_acc(0, stack_at(const_cast<uint64_t*>(stack), l, (int)i)[t * kBlock + j], key);
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+          if (u == t) F[u] += v;
+      }
+    }
+  }
+  // tail words, lane m, m + 64, ...
+  const uint32_t R = (tail_len + 7) / 8;
+  for (uint32_t m = lane; m < R; m += 64) {
+    uint64_t w = 0;
+    if (8 * m + 8 <= tail_len) {
+      __builtin_memcpy(&w, tail + 8 * m, 8);
+    } else {
+      for (uint32_t b = 0; b < tail_len - 8 * m; ++b) w |= (uint64_t)tail[8 * m + b] << (8 * b);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], total_len, ent[Ly::len + t]);
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t) F[t] = wave_sum64(F[t]);
+  if (lane < K) {
+    uint64_t v = F[0];
+#pragma unroll
+    for (int t = 1; t < K; ++t)
+      if (lane == t) v = F[t];
+    __builtin_memcpy(out + 8 * lane, &v, 8);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1094,7 +1228,7 @@ __global__ __launch_bounds__(kProbeThreads) void read_probe_kernel(const uint4* 
 
 const void* main_kernel_fn(uint32_t width, uint32_t block) {
   const void* f = nullptr;
-  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&hash_main_kernel<W, Bk>));
+  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&hash_main_kernel<W, Bk, false>));
   return f;
 }
 
@@ -1135,8 +1269,44 @@ hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32
   // the hashing kernel, then the tail-only strings
   bool known = false;
   HTH_DISPATCH(width, block, {
-    hipLaunchKernelGGL((hash_main_kernel<W, Bk>), dim3(grid), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((hash_main_kernel<W, Bk, false>), dim3(grid), dim3(64), 0, stream, a);
     hipLaunchKernelGGL((tiny_kernel<W, Bk>), dim3(grid), dim3(64), 0, stream, a);
+    known = true;
+  });
+  if (!known) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream) {
+  bool known = false;
+  HTH_DISPATCH(width, block, {
+    hipLaunchKernelGGL((hash_main_kernel<W, Bk, true>), dim3(grid), dim3(64), 0, stream, a);
+    known = true;
+  });
+  if (!known) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
+                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
+                              hipStream_t stream) {
+  bool known = false;
+  HTH_DISPATCH(width, block, {
+    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, roots, levels, nroots, stack,
+                       counts);
+    known = true;
+  });
+  if (!known) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_final(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* stack,
+                               const uint32_t* counts, const uint8_t* tail, uint32_t tail_len, uint64_t total_len,
+                               uint8_t* out, hipStream_t stream) {
+  bool known = false;
+  HTH_DISPATCH(width, block, {
+    hipLaunchKernelGGL((stream_final_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, stack, counts, tail,
+                       tail_len, total_len, out);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;

@@ -206,7 +206,8 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 // Planner and hashing kernel of one batch on `stream`, using workspace `w`.
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
-                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves) {
+                         hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves,
+                         uint64_t* roots) {
   const uint32_t block = seed->block;
   uint32_t grid = 0;
   hth_status st = grid_for(out_width, block, &grid);
@@ -252,9 +253,10 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.gcnt = w.gcnt;
   a.bucket_lead = w.bucket_lead;
   a.tiny_list = w.tiny_list;
+  a.roots = roots;
   a.ctl = w.ctl;
   if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
-  e = hth::launch_main(out_width, block, a, grid, stream);
+  e = roots ? hth::launch_roots(out_width, block, a, grid, stream) : hth::launch_main(out_width, block, a, grid, stream);
   if (e != hipSuccess) return hip_fail(e, "main launch");
   if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;

@@ -1,0 +1,287 @@
+// libhth streaming (hth_stream_* of include/hth.h): one string hashed from
+// pieces appended over time, with the same value hth_hash_batch gives for
+// the whole string.
+//
+// The state is the stack of the tree construction (Eq. (3)): at most 7
+// pending items per level, each k x b words, plus the bytes of the
+// execution still being filled.  Because tree keys depend only on the level,
+// the subtree over an aligned block of 8^L executions (starting at a
+// multiple of 8^L) is the same function of its bytes wherever the block
+// sits.  An update is therefore cut into maximal aligned blocks; the
+// hashing kernel in root mode computes every block's root in one launch
+// (the blocks are its strings), and a one-wave kernel pushes the roots in
+// order onto the device-resident stack.  Finishing hashes the pending items
+// with the final keys, the pending bytes as the tail and the length.  This
+// file only plans blocks and moves bytes; all hash arithmetic is in the
+// kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "hth_host.h"
+#include "hth_kernels.h"
+
+using namespace hth::host;
+
+namespace {
+
+constexpr int kLevelsMax = 20;
+// Aligned blocks of one update: at most 7 per level on the way up to the
+// alignment of the largest block and 7 per level on the way down, plus the
+// execution completed from the carried bytes.
+constexpr uint32_t kMaxRoots = 2 * 7 * kLevelsMax + 8;
+constexpr uint32_t kMaxExecBytes = 8 * 8 * 7 * 3;  // largest execution (b = 8, d = 7, w = 3)
+constexpr uint32_t kSaveMagic = 0x48544853;         // "HTHS"
+constexpr uint32_t kSaveVersion = 1;
+
+struct SaveHeader {
+  uint32_t magic, version, width, block;
+  uint64_t executions, total_len;
+  uint32_t carry_len, reserved;
+};
+
+size_t align_to(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct hth_stream {
+  const hth_seed* seed = nullptr;
+  uint32_t width = 0, block = 8, xb = 0;
+  uint64_t executions = 0;  // full executions absorbed
+  uint64_t total_len = 0;   // bytes appended
+  uint32_t carry_len = 0;   // bytes of the execution being filled
+  void* mem = nullptr;      // device state
+  uint64_t* stack = nullptr;
+  uint32_t* counts = nullptr;
+  uint8_t* carry = nullptr;
+  uint64_t* roots = nullptr;
+  uint64_t* d_off = nullptr;  // [kMaxRoots] block offsets
+  uint64_t* d_len = nullptr;  // [kMaxRoots] block lengths
+  uint32_t* d_lev = nullptr;  // [kMaxRoots] block levels
+  Workspace ws;
+};
+
+namespace {
+
+hth_status stream_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+// Root-mode hashing of `n` blocks starting at host arrays off/len (bytes
+// relative to base), roots to st->roots + first; then nothing else.
+hth_status launch_blocks(hth_stream* st, const uint8_t* base, const uint64_t* off, const uint64_t* len, uint32_t n,
+                         uint32_t first, hipStream_t stream) {
+  if (n == 0) return HTH_OK;
+  hipError_t e = hipMemcpyAsync(st->d_off + first, off, n * 8, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(st->d_len + first, len, n * 8, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table upload");
+  uint64_t waves = 0;
+  for (uint32_t i = 0; i < n; ++i) waves += task_bound(len[i], st->width, st->block);
+  return enqueue_batch(st->seed, base, st->d_off + first, st->d_len + first, n, nullptr, st->width, st->ws, stream,
+                       nullptr, nullptr, waves, st->roots + (uint64_t)first * hth::kMaxK * 8);
+}
+
+}  // namespace
+
+extern "C" {
+
+hth_status hth_stream_create(const hth_seed* seed, uint32_t out_width, hth_stream** out) {
+  if (!out) return fail(HTH_E_INVALID, "hth_stream_create: out is null");
+  *out = nullptr;
+  if (!seed) return fail(HTH_E_INVALID, "hth_stream_create: seed is null");
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_stream_create: out_width %u", out_width);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != seed->device)
+    return fail(HTH_E_INVALID, "hth_stream_create: seed lives on device %d, current is %d", seed->device, dev);
+  hth_stream* st = new (std::nothrow) hth_stream;
+  if (!st) return fail(HTH_E_OOM, "hth_stream_create: host allocation");
+  st->seed = seed;
+  st->width = out_width;
+  st->block = seed->block;
+  st->xb = hth::exec_bytes_of(out_width, seed->block);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_to(off + bytes, 256);
+    return at;
+  };
+  const size_t o_stack = take((size_t)hth::kStackWords * 8);
+  const size_t o_counts = take(32 * 4);
+  const size_t o_carry = take(kMaxExecBytes);
+  const size_t o_roots = take((size_t)kMaxRoots * hth::kMaxK * 8 * 8);
+  const size_t o_off = take(kMaxRoots * 8);
+  const size_t o_len = take(kMaxRoots * 8);
+  const size_t o_lev = take(kMaxRoots * 4);
+  e = hipMalloc(&st->mem, off);
+  if (e == hipSuccess) e = hipMemset(st->mem, 0, off);
+  if (e != hipSuccess) {
+    if (st->mem) (void)hipFree(st->mem);
+    delete st;
+    return hip_fail(e, "hth_stream_create: state allocation");
+  }
+  char* b = static_cast<char*>(st->mem);
+  st->stack = reinterpret_cast<uint64_t*>(b + o_stack);
+  st->counts = reinterpret_cast<uint32_t*>(b + o_counts);
+  st->carry = reinterpret_cast<uint8_t*>(b + o_carry);
+  st->roots = reinterpret_cast<uint64_t*>(b + o_roots);
+  st->d_off = reinterpret_cast<uint64_t*>(b + o_off);
+  st->d_len = reinterpret_cast<uint64_t*>(b + o_len);
+  st->d_lev = reinterpret_cast<uint32_t*>(b + o_lev);
+  hth_status s = ws_alloc(st->ws, kMaxRoots, nullptr);
+  if (s != HTH_OK) {
+    (void)hipFree(st->mem);
+    delete st;
+    return s;
+  }
+  *out = st;
+  return HTH_OK;
+}
+
+hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len, hipStream_t stream) {
+  if (!st) return fail(HTH_E_INVALID, "hth_stream_update: stream is null");
+  if (len && !bytes) return fail(HTH_E_INVALID, "hth_stream_update: bytes is null");
+  if (len == 0) return HTH_OK;
+  const uint64_t xb = st->xb;
+  hipError_t e;
+  if (st->carry_len + len < xb) {
+    e = hipMemcpyAsync(st->carry + st->carry_len, bytes, len, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
+    st->carry_len += (uint32_t)len;
+    st->total_len += len;
+    return HTH_OK;
+  }
+  // 1. the execution completed from the carried bytes (a block of level 0)
+  uint64_t pos = 0, e0 = st->executions;
+  uint32_t nroots = 0;
+  std::vector<uint32_t> levels;
+  levels.reserve(kMaxRoots);
+  if (st->carry_len) {
+    pos = xb - st->carry_len;
+    e = hipMemcpyAsync(st->carry + st->carry_len, bytes, pos, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
+    const uint64_t o = 0, l = xb;
+    hth_status s = launch_blocks(st, st->carry, &o, &l, 1, 0, stream);
+    if (s != HTH_OK) return s;
+    levels.push_back(0);
+    nroots = 1;
+    ++e0;
+  }
+  // 2. the update's full executions, cut into maximal aligned blocks
+  const uint64_t n = (len - pos) / xb;
+  std::vector<uint64_t> boff, blen;
+  for (uint64_t x = e0, end = e0 + n; x < end;) {
+    int L = 0;
+    while (L + 1 < kLevelsMax && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
+    const uint64_t cnt = 1ull << (3 * L);
+    boff.push_back(pos + (x - e0) * xb);
+    blen.push_back(cnt * xb);
+    levels.push_back((uint32_t)L);
+    x += cnt;
+  }
+  hth_status s = launch_blocks(st, bytes, boff.data(), blen.data(), (uint32_t)boff.size(), nroots, stream);
+  if (s != HTH_OK) return s;
+  nroots += (uint32_t)boff.size();
+  // 3. push the roots in order
+  e = hipMemcpyAsync(st->d_lev, levels.data(), nroots * 4, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: level table upload");
+  const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
+  e = hth::launch_stream_push(st->width, st->block, ent, st->roots, st->d_lev, nroots, st->stack, st->counts, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
+  // 4. the bytes after the last full execution start the next one
+  const uint64_t rem = len - pos - n * xb;
+  if (rem) {
+    e = hipMemcpyAsync(st->carry, bytes + pos + n * xb, rem, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
+  }
+  st->carry_len = (uint32_t)rem;
+  st->executions = e0 + n;
+  st->total_len += len;
+  return HTH_OK;
+}
+
+hth_status hth_stream_final(hth_stream* st, uint8_t* out, hipStream_t stream) {
+  if (!st || !out) return fail(HTH_E_INVALID, "hth_stream_final: null pointer");
+  const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
+  hipError_t e = hth::launch_stream_final(st->width, st->block, ent, st->stack, st->counts, st->carry, st->carry_len,
+                                          st->total_len, out, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_final: launch");
+  return HTH_OK;
+}
+
+hth_status hth_stream_reset(hth_stream* st, hipStream_t stream) {
+  if (!st) return fail(HTH_E_INVALID, "hth_stream_reset: stream is null");
+  hipError_t e = hipMemsetAsync(st->counts, 0, 32 * 4, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_reset");
+  st->executions = st->total_len = 0;
+  st->carry_len = 0;
+  return HTH_OK;
+}
+
+hth_status hth_stream_save(hth_stream* st, void* host, size_t* size, hipStream_t stream) {
+  if (!st || !size) return fail(HTH_E_INVALID, "hth_stream_save: null pointer");
+  const size_t need = sizeof(SaveHeader) + kLevelsMax * 4 + (size_t)hth::kStackWords * 8 + st->xb;
+  if (!host) {
+    *size = need;
+    return HTH_OK;
+  }
+  if (*size < need) return fail(HTH_E_TOO_LARGE, "hth_stream_save: buffer of %zu bytes, %zu needed", *size, need);
+  SaveHeader h{kSaveMagic, kSaveVersion, st->width, st->block, st->executions, st->total_len, st->carry_len, 0};
+  char* p = static_cast<char*>(host);
+  std::memcpy(p, &h, sizeof h);
+  hipError_t e = hipMemcpyAsync(p + sizeof h, st->counts, kLevelsMax * 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p + sizeof h + kLevelsMax * 4, st->stack, (size_t)hth::kStackWords * 8, hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p + sizeof h + kLevelsMax * 4 + (size_t)hth::kStackWords * 8, st->carry, st->xb,
+                       hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_save");
+  *size = need;
+  return HTH_OK;
+}
+
+hth_status hth_stream_load(hth_stream* st, const void* host, size_t size, hipStream_t stream) {
+  if (!st || !host) return fail(HTH_E_INVALID, "hth_stream_load: null pointer");
+  const size_t need = sizeof(SaveHeader) + kLevelsMax * 4 + (size_t)hth::kStackWords * 8 + st->xb;
+  SaveHeader h;
+  if (size < sizeof h) return fail(HTH_E_INVALID, "hth_stream_load: %zu bytes is too short", size);
+  std::memcpy(&h, host, sizeof h);
+  if (h.magic != kSaveMagic || h.version != kSaveVersion)
+    return fail(HTH_E_INVALID, "hth_stream_load: not a saved stream state");
+  if (h.width != st->width || h.block != st->block)
+    return fail(HTH_E_INVALID, "hth_stream_load: state of width %u / block %u, stream is %u / %u", h.width, h.block,
+                st->width, st->block);
+  if (size < need || h.carry_len >= st->xb) return fail(HTH_E_INVALID, "hth_stream_load: truncated or corrupt state");
+  const char* p = static_cast<const char*>(host);
+  hipError_t e = hipMemcpyAsync(st->counts, p + sizeof h, kLevelsMax * 4, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st->stack, p + sizeof h + kLevelsMax * 4, (size_t)hth::kStackWords * 8, hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st->carry, p + sizeof h + kLevelsMax * 4 + (size_t)hth::kStackWords * 8, st->xb,
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_load");
+  st->executions = h.executions;
+  st->total_len = h.total_len;
+  st->carry_len = h.carry_len;
+  return HTH_OK;
+}
+
+uint64_t hth_stream_length(const hth_stream* st) { return st ? st->total_len : 0; }
+
+hth_status hth_stream_free(hth_stream* st) {
+  if (!st) return HTH_OK;
+  hipError_t e = hipFree(st->mem);
+  if (st->ws.mem) {
+    hipError_t f = hipFree(st->ws.mem);
+    if (e == hipSuccess) e = f;
+  }
+  delete st;
+  if (e != hipSuccess) return hip_fail(e, "hth_stream_free");
+  return HTH_OK;
+}
+
+}  // extern "C"

@@ -30,7 +30,9 @@ SYMBOLS = (
     "hth_batch_graph_check", "hth_batch_graph_free", "hth_serve_create", "hth_serve_submit",
     "hth_serve_poll", "hth_serve_wait", "hth_serve_wait_many", "hth_serve_replay", "hth_serve_stats",
     "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause", "hth_read_probe", "hth_entropy_words_b",
-    "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words",
+    "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words", "hth_stream_create",
+    "hth_stream_update", "hth_stream_final", "hth_stream_reset", "hth_stream_save", "hth_stream_load",
+    "hth_stream_length", "hth_stream_free",
 )
 
 
@@ -102,10 +104,19 @@ def lib():
         L.hth_expand_seed_b.argtypes = [u64, u32, ctypes.POINTER(vp), vp]
         L.hth_seed_from_entropy_b.argtypes = [vp, ctypes.c_size_t, u32, ctypes.POINTER(vp), vp]
         L.hth_seed_block_words.argtypes = [vp]
+        L.hth_stream_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
+        L.hth_stream_update.argtypes = [vp, vp, u64, vp]
+        L.hth_stream_final.argtypes = [vp, vp, vp]
+        L.hth_stream_reset.argtypes = [vp, vp]
+        L.hth_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t), vp]
+        L.hth_stream_load.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.hth_stream_length.argtypes = [vp]
+        L.hth_stream_free.argtypes = [vp]
         for name in SYMBOLS[2:]:
             getattr(L, name).restype = ctypes.c_int32
         L.hth_entropy_words_b.restype = ctypes.c_size_t
         L.hth_seed_block_words.restype = ctypes.c_uint32
+        L.hth_stream_length.restype = ctypes.c_uint64
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
                      "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning",
                      "hth_batch_graph_create", "hth_batch_graph_launch", "hth_batch_graph_check",
@@ -404,5 +415,63 @@ class Server:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """One string hashed from pieces appended over time (hth_stream_*); the
+    value equals hash_batch's for the concatenation of the pieces."""
+
+    def __init__(self, seed, out_width):
+        self._seed = seed
+        self.out_width = out_width
+        h = ctypes.c_void_p()
+        _check(lib().hth_stream_create(seed.handle, out_width, ctypes.byref(h)))
+        self._h = h
+
+    def update(self, data, stream=None):
+        """Append a uint8 CUDA tensor (it must stay alive until the work
+        enqueued on the stream completes)."""
+        import torch
+        if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():
+            raise TypeError("data must be a contiguous uint8 CUDA tensor")
+        _check(lib().hth_stream_update(self._h, ctypes.c_void_p(data.data_ptr() if data.numel() else 0),
+                                       data.numel(), _stream(stream)))
+        return self
+
+    def final(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.out_width, dtype=torch.uint8, device="cuda")
+        _check(lib().hth_stream_final(self._h, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def reset(self, stream=None):
+        _check(lib().hth_stream_reset(self._h, _stream(stream)))
+
+    def save(self, stream=None):
+        """The state as bytes (a checkpoint)."""
+        n = ctypes.c_size_t()
+        _check(lib().hth_stream_save(self._h, None, ctypes.byref(n), _stream(stream)))
+        buf = (ctypes.c_uint8 * n.value)()
+        _check(lib().hth_stream_save(self._h, buf, ctypes.byref(n), _stream(stream)))
+        return bytes(buf)
+
+    def load(self, state, stream=None):
+        buf = (ctypes.c_uint8 * len(state)).from_buffer_copy(state)
+        _check(lib().hth_stream_load(self._h, buf, len(state), _stream(stream)))
+
+    def __len__(self):
+        return int(lib().hth_stream_length(self._h))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            lib().hth_stream_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
         except Exception:
             pass

@@ -117,3 +117,17 @@ def test_block_size_entry_points(lib):
     assert lib.hth_seed_from_entropy_b(words, 10229, 8, ctypes.byref(h), None) == hth.HTH_E_INVALID
     assert lib.hth_seed_from_entropy_b(words, 10229, 3, ctypes.byref(h), None) == hth.HTH_E_INVALID
     assert lib.hth_seed_block_words(None) == 0
+
+
+def test_stream_argument_checks(lib):
+    """hth_stream_* reject bad arguments before any device use."""
+    from paper_2104_08865_amd import hth
+    h = ctypes.c_void_p()
+    assert lib.hth_stream_create(None, 24, ctypes.byref(h)) == hth.HTH_E_INVALID
+    assert lib.hth_stream_create(ctypes.c_void_p(1), 24, None) == hth.HTH_E_INVALID
+    assert lib.hth_stream_update(None, None, 0, None) == hth.HTH_E_INVALID
+    assert lib.hth_stream_final(None, None, None) == hth.HTH_E_INVALID
+    n = ctypes.c_size_t()
+    assert lib.hth_stream_save(None, None, ctypes.byref(n), None) == hth.HTH_E_INVALID
+    assert lib.hth_stream_length(None) == 0
+    assert lib.hth_stream_free(None) == hth.HTH_OK

@@ -1,0 +1,117 @@
+"""Streaming (hth_stream_*): a string appended in pieces of any size hashes
+to the batch value of the whole string (and the oracle's), in both
+families, across save/load; pieces are device tensors."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2104_08865_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def env(oracle_lib):
+    import torch
+    from paper_2104_08865_amd import hth
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return {"torch": torch, "hth": hth, "oracle": oracle_lib}
+
+
+def _pieces(rng, total, xb):
+    """Piece lengths: empty, tiny, around one execution, large; summing to total."""
+    out, at = [], 0
+    while at < total:
+        kind = rng.integers(0, 5)
+        cap = [0, 60, xb + 3, 9 * xb, 700 * xb][kind]
+        n = int(min(total - at, rng.integers(0, cap + 1)))
+        out.append(n)
+        at += n
+    return out
+
+
+@pytest.mark.parametrize("block", [8, 4])
+@pytest.mark.parametrize("width", [16, 24, 32, 40])
+def test_stream_equals_batch_and_oracle(env, width, block):
+    torch, hth, o = env["torch"], env["hth"], env["oracle"]
+    seed = hth.expand_seed(41, block_words=block)
+    ent = o.expand_seed(41, b=block)
+    xb = wl.execution_bytes(width) * block // 8
+    total = 3_000_000 + width
+    data_np = wl.random_bytes(42, total)
+    data = torch.from_numpy(data_np).cuda()
+    rng = np.random.default_rng(width + block)
+    pieces = _pieces(rng, total, xb)
+    print(f"[stream] width={width} b={block} bytes={total} pieces={len(pieces)}", flush=True)
+    st = hth.Stream(seed, width)
+    at = 0
+    mids = []
+    for i, n in enumerate(pieces):
+        st.update(data[at:at + n])
+        at += n
+        if i % 7 == 3:  # intermediate values: the hash of the prefix so far
+            mids.append((at, st.final().clone()))
+    got = st.final().cpu().numpy()
+    assert len(st) == total
+    torch.cuda.synchronize()
+    whole = hth.hash_batch(seed, data, torch.zeros(1, dtype=torch.int64, device="cuda"),
+                           torch.full((1,), total, dtype=torch.int64, device="cuda"), width).cpu().numpy()[0]
+    assert (got == whole).all()
+    assert (got == o.hash_bytes(ent, data_np, width, b=block)).all()
+    for at, h in mids[:4]:
+        assert (h.cpu().numpy() == o.hash_bytes(ent, data_np[:at], width, b=block)).all(), at
+    st.free()
+
+
+def test_stream_save_load_reset(env):
+    """A checkpoint taken mid-string resumes in another stream object; reset
+    returns to the empty string; a state refuses a stream of another width."""
+    torch, hth, o = env["torch"], env["hth"], env["oracle"]
+    seed = hth.expand_seed(43)
+    ent = o.expand_seed(43)
+    data_np = wl.random_bytes(44, 900_001)
+    data = torch.from_numpy(data_np).cuda()
+    a = hth.Stream(seed, 32)
+    a.update(data[:123_457])
+    state = a.save()
+    b = hth.Stream(seed, 32)
+    b.load(state)
+    for s in (a, b):
+        s.update(data[123_457:])
+    ref = o.hash_bytes(ent, data_np, 32)
+    assert (a.final().cpu().numpy() == ref).all()
+    assert (b.final().cpu().numpy() == ref).all()
+    a.reset()
+    a.update(data[:5])
+    assert (a.final().cpu().numpy() == o.hash_bytes(ent, data_np[:5], 32)).all()
+    empty = hth.Stream(seed, 32)
+    assert (empty.final().cpu().numpy() == o.hash_bytes(ent, b"", 32)).all()
+    other = hth.Stream(seed, 24)
+    with pytest.raises(hth.HthError):
+        other.load(state)
+    for s in (a, b, empty, other):
+        s.free()
+
+
+def test_stream_long_string_pieces(env):
+    """A 1 GiB string appended in 37 uneven pieces (blocks up to level 6)."""
+    torch, hth, o = env["torch"], env["hth"], env["oracle"]
+    seed = hth.expand_seed(45)
+    sz = 1 << 30
+    data = wl.random_bytes_torch(46, sz, "cuda")
+    rng = np.random.default_rng(46)
+    cuts = np.sort(rng.integers(1, sz, 36))
+    st = hth.Stream(seed, 24)
+    prev = 0
+    for c in list(cuts) + [sz]:
+        st.update(data[prev:int(c)])
+        prev = int(c)
+    got = st.final().cpu().numpy()
+    whole = hth.hash_batch(seed, data, torch.zeros(1, dtype=torch.int64, device="cuda"),
+                           torch.full((1,), sz, dtype=torch.int64, device="cuda"), 24).cpu().numpy()[0]
+    assert (got == whole).all()
+    st.free()
+    del data
+    torch.cuda.empty_cache()
