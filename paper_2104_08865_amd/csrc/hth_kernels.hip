@@ -1120,6 +1120,34 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
   if (lane < kLevels) counts[lane] = cnt;
 }
 
+// The block table of one update: optionally the execution completed from
+// carried bytes (entry 0: offset 0, one execution, level 0), then the
+// maximal aligned blocks of executions e0 .. e0 + n - 1 (block offsets
+// relative to the update's bytes, starting `pos` bytes in).  One thread: a
+// few hundred entries at most; it keeps the table off the host path.
+__global__ void stream_table_kernel(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint32_t has_carry,
+                                    uint64_t* __restrict__ off, uint64_t* __restrict__ len,
+                                    uint32_t* __restrict__ lev) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t i = 0;
+  if (has_carry) {
+    off[0] = 0;
+    len[0] = xb;
+    lev[0] = 0;
+    i = 1;
+  }
+  for (uint64_t x = e0, end = e0 + n; x < end;) {
+    int L = 0;
+    while (L + 1 < kLevels && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
+    const uint64_t cnt = 1ull << (3 * L);
+    off[i] = pos + (x - e0) * xb;
+    len[i] = cnt * xb;
+    lev[i] = (uint32_t)L;
+    ++i;
+    x += cnt;
+  }
+}
+
 // The hash of everything pushed so far plus the pending tail bytes: the
 // final NH over the pending items (§5.2), the Toeplitz tail (§6.1) and the
 // length term, as the batch kernel computes them.
@@ -1297,6 +1325,12 @@ hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* en
     known = true;
   });
   if (!known) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint32_t has_carry, uint64_t* off,
+                               uint64_t* len, uint32_t* lev, hipStream_t stream) {
+  hipLaunchKernelGGL(stream_table_kernel, dim3(1), dim3(64), 0, stream, e0, n, pos, xb, has_carry, off, len, lev);
   return hipGetLastError();
 }
 

@@ -17,7 +17,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
-#include <vector>
 
 #include "hth_host.h"
 #include "hth_kernels.h"
@@ -66,16 +65,12 @@ namespace {
 
 hth_status stream_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
 
-// Root-mode hashing of `n` blocks starting at host arrays off/len (bytes
-// relative to base), roots to st->roots + first; then nothing else.
-hth_status launch_blocks(hth_stream* st, const uint8_t* base, const uint64_t* off, const uint64_t* len, uint32_t n,
-                         uint32_t first, hipStream_t stream) {
+// Root-mode hashing of the n blocks whose table entries start at `first`
+// (bytes relative to base); roots to st->roots + first.  waves: an upper
+// bound of their tasks.
+hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint32_t first, uint64_t waves,
+                         hipStream_t stream) {
   if (n == 0) return HTH_OK;
-  hipError_t e = hipMemcpyAsync(st->d_off + first, off, n * 8, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(st->d_len + first, len, n * 8, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table upload");
-  uint64_t waves = 0;
-  for (uint32_t i = 0; i < n; ++i) waves += task_bound(len[i], st->width, st->block);
   return enqueue_batch(st->seed, base, st->d_off + first, st->d_len + first, n, nullptr, st->width, st->ws, stream,
                        nullptr, nullptr, waves, st->roots + (uint64_t)first * hth::kMaxK * 8);
 }
@@ -153,38 +148,34 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   }
   // 1. the execution completed from the carried bytes (a block of level 0)
   uint64_t pos = 0, e0 = st->executions;
-  uint32_t nroots = 0;
-  std::vector<uint32_t> levels;
-  levels.reserve(kMaxRoots);
-  if (st->carry_len) {
+  const uint32_t has_carry = st->carry_len ? 1 : 0;
+  if (has_carry) {
     pos = xb - st->carry_len;
     e = hipMemcpyAsync(st->carry + st->carry_len, bytes, pos, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
-    const uint64_t o = 0, l = xb;
-    hth_status s = launch_blocks(st, st->carry, &o, &l, 1, 0, stream);
-    if (s != HTH_OK) return s;
-    levels.push_back(0);
-    nroots = 1;
     ++e0;
   }
-  // 2. the update's full executions, cut into maximal aligned blocks
+  // 2. the update's full executions, cut into maximal aligned blocks: the
+  // table is written on the device; the host only counts its entries
   const uint64_t n = (len - pos) / xb;
-  std::vector<uint64_t> boff, blen;
+  uint32_t nblocks = 0;
+  uint64_t waves = 0;
   for (uint64_t x = e0, end = e0 + n; x < end;) {
     int L = 0;
     while (L + 1 < kLevelsMax && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
     const uint64_t cnt = 1ull << (3 * L);
-    boff.push_back(pos + (x - e0) * xb);
-    blen.push_back(cnt * xb);
-    levels.push_back((uint32_t)L);
+    waves += task_bound(cnt * xb, st->width, st->block);
+    ++nblocks;
     x += cnt;
   }
-  hth_status s = launch_blocks(st, bytes, boff.data(), blen.data(), (uint32_t)boff.size(), nroots, stream);
+  e = hth::launch_stream_table(e0, n, pos, xb, has_carry, st->d_off, st->d_len, st->d_lev, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
+  hth_status s = launch_blocks(st, st->carry, has_carry, 0, 1, stream);
   if (s != HTH_OK) return s;
-  nroots += (uint32_t)boff.size();
+  s = launch_blocks(st, bytes, nblocks, has_carry, waves, stream);
+  if (s != HTH_OK) return s;
   // 3. push the roots in order
-  e = hipMemcpyAsync(st->d_lev, levels.data(), nroots * 4, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: level table upload");
+  const uint32_t nroots = has_carry + nblocks;
   const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
   e = hth::launch_stream_push(st->width, st->block, ent, st->roots, st->d_lev, nroots, st->stack, st->counts, stream);
   if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
