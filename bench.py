@@ -210,7 +210,7 @@ def run_throughput(args):
         algo = n * sz + 16 * n + w * n  # input bytes + offsets/lengths + output
         achieved = algo / (ms * 1e-3) / 1e9
         per_width[str(w)] = {
-            "kernel": f"hth::hash_main_kernel<{w}>",
+            "kernel": f"hth::hash_main_kernel<{w}, {b}, false>",
             "avg_ms": ms,
             "median_ms": float(np.median(samples)),
             "median_GBps": algo / (float(np.median(samples)) * 1e-3) / 1e9,
@@ -487,7 +487,7 @@ def _uneven_line(args, total, count, wall, gwall, swall, kernel_ms, width, choic
                                "0..520, packed back to back (splitmix64 seed 3), width 24, one persistent launch",
                    "strings": int(count), "bytes": int(total), "width": width, "seed": 3,
                    "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
-        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms,
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}, 8, false>", algo, kernel_ms,
                               measured_traffic(width, UNEVEN_TRAFFIC_FILE) if choice in DEFAULT_CHOICES else None),
         "graph_replay_GBps": total * args.steps / gwall / 1e9,
         "per_string_launches_GBps": total / swall / 1e9 if swall else None,
@@ -563,7 +563,7 @@ def run_long(args):
         "config": {"workload": "one 8 GiB string of uniform random bytes (splitmix64 seed 4), width 32",
                    "bytes": sz, "width": width, "seed": 4,
                    "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
-        "roofline": _roofline(f"hth::hash_main_kernel<{width}>", algo, kernel_ms),
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}, 8, false>", algo, kernel_ms),
         "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
         "streaming": streaming,
         "cpu_baseline": cpu,
