@@ -66,6 +66,14 @@ def lib():
         L.hth_ref_hash_b.argtypes = [u64p, ctypes.c_size_t, u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u8p]
         L.hth_ref_hash_batch_b.argtypes = [u64p, ctypes.c_size_t, u8p, u64p, u64p, ctypes.c_uint64,
                                            ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint32]
+        L.hth_ref_tab_words.restype = ctypes.c_size_t
+        L.hth_ref_tab_words.argtypes = [ctypes.c_uint32]
+        L.hth_ref_tab_expand.argtypes = [ctypes.c_uint64, ctypes.c_uint32, u64p]
+        L.hth_ref_hash64_b.argtypes = [u64p, ctypes.c_size_t, u64p, ctypes.c_size_t, u8p, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_uint32, u64p]
+        L.hth_ref_hash64_batch_b.argtypes = [u64p, ctypes.c_size_t, u64p, ctypes.c_size_t, u8p, u64p, u64p,
+                                             ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u64p,
+                                             ctypes.c_uint32]
         _lib = L
     return _lib
 
@@ -203,3 +211,50 @@ def mul_counts():
     out = np.zeros(5, dtype=np.uint64)
     lib().hth_ref_mul_counts(_p64(out))
     return dict(zip(("ehc", "tree", "final", "tail", "length"), (int(x) for x in out)))
+
+
+def tab_words(width):
+    """Words of the tabulation tables for inner width c: (c + 1) * 256."""
+    n = int(lib().hth_ref_tab_words(width))
+    if not n:
+        raise ValueError(width)
+    return n
+
+
+def tab_expand(user_seed, width):
+    """Tabulation tables from splitmix64 started at user_seed, shape (c + 1, 256)."""
+    out = np.zeros(tab_words(width), dtype=np.uint64)
+    if lib().hth_ref_tab_expand(ctypes.c_uint64(user_seed & (2**64 - 1)), width, _p64(out)):
+        raise ValueError(width)
+    return out.reshape(width + 1, 256)
+
+
+def hash64(entropy, tables, data, width, b=8):
+    """The composed 64-bit hash of one byte string (simple tabulation of the
+    string itself when it has at most `width` bytes, else of its HalftimeHash
+    value); returns an int."""
+    ent = _u64(entropy)
+    tab = _u64(tables).ravel()
+    data = np.ascontiguousarray(np.frombuffer(bytes(data), dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else data, dtype=np.uint8)
+    out = np.zeros(1, dtype=np.uint64)
+    dp = _p8(data) if data.size else ctypes.POINTER(ctypes.c_uint8)()
+    if lib().hth_ref_hash64_b(_p64(ent), ent.size, _p64(tab), tab.size, dp, data.size, width, b, _p64(out)):
+        raise ValueError("hth_ref_hash64 rejected its arguments")
+    return int(out[0])
+
+
+def hash64_batch(entropy, tables, data, offsets, lengths, width, nthreads=1, b=8):
+    """The composed 64-bit hash of many strings of one buffer; returns (count,) uint64."""
+    ent = _u64(entropy)
+    tab = _u64(tables).ravel()
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    offsets = _u64(offsets); lengths = _u64(lengths)
+    count = offsets.size
+    out = np.zeros(count, dtype=np.uint64)
+    if count:
+        assert int((offsets + lengths).max()) <= data.size
+    dp = _p8(data) if data.size else ctypes.POINTER(ctypes.c_uint8)()
+    if lib().hth_ref_hash64_batch_b(_p64(ent), ent.size, _p64(tab), tab.size, dp, _p64(offsets), _p64(lengths),
+                                    count, width, b, _p64(out), nthreads):
+        raise ValueError("hth_ref_hash64_batch rejected its arguments")
+    return out

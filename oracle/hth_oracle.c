@@ -575,3 +575,97 @@ int hth_ref_hash_batch(const uint64_t *entropy, size_t n_words, const uint8_t *d
     return hth_ref_hash_batch_b(entropy, n_words, data, offsets, lengths, count, out_width, HTH_REF_B, out,
                                 nthreads);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Composition with simple tabulation (§1, §7 future work).                  */
+/* ------------------------------------------------------------------------ */
+
+size_t hth_ref_tab_words(uint32_t inner_width)
+{
+    return shape_of(inner_width) ? (size_t)(inner_width + 1) * 256 : 0;
+}
+
+int hth_ref_tab_expand(uint64_t user_seed, uint32_t inner_width, uint64_t *tables)
+{
+    size_t n = hth_ref_tab_words(inner_width);
+    if (!n || !tables) return -1;
+    uint64_t state = user_seed;
+    for (size_t i = 0; i < n; i++) {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        tables[i] = z ^ (z >> 31);
+    }
+    return 0;
+}
+
+int hth_ref_hash64_b(const uint64_t *entropy, size_t n_words, const uint64_t *tables, size_t n_tab,
+                     const uint8_t *data, uint64_t len, uint32_t inner_width, uint32_t b, uint64_t *out)
+{
+    const uint32_t c = inner_width;
+    if (!hth_ref_tab_words(c) || n_tab != hth_ref_tab_words(c) || !tables || !out) return -1;
+    if (len && !data) return -1;
+    /* the key: c characters and the separator character c */
+    uint8_t key[41];
+    if (len <= c) {
+        for (uint32_t i = 0; i < c; i++) key[i] = i < len ? data[i] : 0;
+        key[c] = (uint8_t)len;
+    } else {
+        int rc = hth_ref_hash_b(entropy, n_words, data, len, c, b, key);
+        if (rc) return rc;
+        key[c] = 255;
+    }
+    /* simple tabulation: one table per character, results XORed */
+    uint64_t z = 0;
+    for (uint32_t i = 0; i <= c; i++) z ^= tables[(size_t)i * 256 + key[i]];
+    *out = z;
+    return 0;
+}
+
+typedef struct {
+    const uint64_t *entropy, *tables;
+    size_t n_words, n_tab;
+    const uint8_t *data;
+    const uint64_t *offsets, *lengths;
+    uint64_t count;
+    uint32_t width, b;
+    uint64_t *out;
+    uint32_t nthreads, id;
+    int rc;
+} hash64_job;
+
+static void *hash64_worker(void *arg)
+{
+    hash64_job *jb = arg;
+    jb->rc = 0;
+    for (uint64_t i = jb->id; i < jb->count; i += jb->nthreads) {
+        int rc = hth_ref_hash64_b(jb->entropy, jb->n_words, jb->tables, jb->n_tab, jb->data + jb->offsets[i],
+                                  jb->lengths[i], jb->width, jb->b, jb->out + i);
+        if (rc) jb->rc = rc;
+    }
+    return NULL;
+}
+
+int hth_ref_hash64_batch_b(const uint64_t *entropy, size_t n_words, const uint64_t *tables, size_t n_tab,
+                           const uint8_t *data, const uint64_t *offsets, const uint64_t *lengths,
+                           uint64_t count, uint32_t inner_width, uint32_t b, uint64_t *out, uint32_t nthreads)
+{
+    if (!hth_ref_tab_words(inner_width) || !block_ok(b) || (count && (!offsets || !lengths || !out))) return -1;
+    if (nthreads == 0) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    hash64_job jobs[256];
+    pthread_t th[256];
+    for (uint32_t i = 0; i < nthreads; i++) {
+        jobs[i] = (hash64_job){entropy, tables, n_words, n_tab, data, offsets, lengths, count, inner_width, b, out,
+                               nthreads, i, 0};
+        if (nthreads == 1) hash64_worker(&jobs[i]);
+        else pthread_create(&th[i], NULL, hash64_worker, &jobs[i]);
+    }
+    int rc = 0;
+    for (uint32_t i = 0; i < nthreads; i++) {
+        if (nthreads > 1) pthread_join(th[i], NULL);
+        if (jobs[i].rc) rc = jobs[i].rc;
+    }
+    return rc;
+}

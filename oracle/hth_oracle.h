@@ -116,6 +116,34 @@ int hth_ref_hash_batch_b(const uint64_t *entropy, size_t n_words,
                          uint32_t out_width, uint32_t b, uint8_t *out,
                          uint32_t nthreads);
 
+/* Composition with a short-input family (§1: a universe-collapsing family
+   reduces long strings to a few bytes that a short-input family then hashes
+   as if they were the input; §7 lists pairing HalftimeHash with a fast
+   short-input family as future work).  The short-input family is simple
+   tabulation over c + 1 byte characters, c = inner_width (16/24/32/40):
+   tables[i*256 + v] = T_i[v] for i in [0, c].  The key of a string x of L
+   bytes is
+     L <= c:  chars 0..c-1 = x zero-padded to c bytes, char c = L;
+     L >  c:  chars 0..c-1 = the c bytes of HalftimeHash (inner width c,
+              block size b) of x, char c = 255;
+   and the 64-bit result is the XOR of T_i[char i] over i = 0..c.  The two
+   kinds of key always differ in char c.
+   hth_ref_tab_words: (c + 1) * 256, or 0 for an unsupported width.
+   hth_ref_tab_expand: tables[i] = i-th output of splitmix64 started at
+   user_seed (the same generator as the entropy expansion; use a seed
+   independent of the hashing seed's). */
+size_t hth_ref_tab_words(uint32_t inner_width);
+int hth_ref_tab_expand(uint64_t user_seed, uint32_t inner_width, uint64_t *tables);
+int hth_ref_hash64_b(const uint64_t *entropy, size_t n_words, const uint64_t *tables,
+                     size_t n_tab, const uint8_t *data, uint64_t len,
+                     uint32_t inner_width, uint32_t b, uint64_t *out);
+int hth_ref_hash64_batch_b(const uint64_t *entropy, size_t n_words,
+                           const uint64_t *tables, size_t n_tab,
+                           const uint8_t *data, const uint64_t *offsets,
+                           const uint64_t *lengths, uint64_t count,
+                           uint32_t inner_width, uint32_t b, uint64_t *out,
+                           uint32_t nthreads);
+
 /* Multiplication counters of the last hth_ref_hash_words / hth_ref_hash call
    on this thread: {ehc, tree, final, tail, length}. */
 void hth_ref_mul_counts(uint64_t out[5]);

@@ -34,6 +34,14 @@ def cases():
                     yield b, user_seed, width, n
 
 
+def composed_cases():
+    for b in (8, 4):
+        for width in (16, 24, 32, 40):
+            xb = wl.execution_bytes(width) * b // 8
+            for n in (0, 1, 8, width - 1, width, width + 1, 100, xb - 1, xb, 8 * xb + 3):
+                yield b, 1, 2, width, n
+
+
 def main():
     rows = []
     ents = {}
@@ -46,17 +54,28 @@ def main():
         if b != 8:
             row["block_words"] = b
         rows.append(row)
+    composed = []
+    for b, user_seed, tab_seed, width, n in composed_cases():
+        if (b, user_seed) not in ents:
+            ents[(b, user_seed)] = oracle.expand_seed(user_seed, b=b)
+        data = wl.random_bytes(1, n)
+        z = oracle.hash64(ents[(b, user_seed)], oracle.tab_expand(tab_seed, width), data.tobytes(), width, b=b)
+        composed.append({"user_seed": user_seed, "tab_seed": tab_seed, "width": width, "length": n,
+                         "bytes_seed": 1, "block_words": b, "hash64": f"{z:016x}"})
     doc = {
         "about": "HalftimeHash values of the frozen family, written by tests/golden/make_golden.py "
                  "from the CPU oracle; data = first `length` bytes of the splitmix64 byte buffer "
                  "with seed `bytes_seed`; entropy = splitmix64 expansion of `user_seed`; "
-                 "`block_words` (default 8) is the family's block size b.",
+                 "`block_words` (default 8) is the family's block size b.  `composed`: the 64-bit "
+                 "composition with simple tabulation (inner width `width`, tables = splitmix64 "
+                 "expansion of `tab_seed`), as a hexadecimal integer.",
         "cases": rows,
+        "composed": composed,
     }
     with open(OUT, "w") as f:
         json.dump(doc, f, indent=1)
         f.write("\n")
-    print(f"wrote {len(rows)} cases to {OUT}")
+    print(f"wrote {len(rows)} cases and {len(composed)} composed cases to {OUT}")
 
 
 if __name__ == "__main__":

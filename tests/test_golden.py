@@ -18,3 +18,14 @@ def test_oracle_matches_golden(oracle_lib):
         data = wl.random_bytes(row["bytes_seed"], row["length"])
         h = oracle_lib.hash_bytes(ents[(s, b)], data.tobytes(), row["width"], b=b)
         assert bytes(h).hex() == row["hash"], row
+
+
+def test_oracle_matches_golden_composed(oracle_lib):
+    doc = json.load(open(GOLDEN))
+    assert len(doc["composed"]) == 80
+    for row in doc["composed"]:
+        ent = oracle_lib.expand_seed(row["user_seed"], b=row["block_words"])
+        tab = oracle_lib.tab_expand(row["tab_seed"], row["width"])
+        data = wl.random_bytes(row["bytes_seed"], row["length"])
+        z = oracle_lib.hash64(ent, tab, data.tobytes(), row["width"], b=row["block_words"])
+        assert f"{z:016x}" == row["hash64"], row

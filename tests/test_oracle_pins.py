@@ -648,3 +648,109 @@ def test_b4_zero_entropy_one_word(oracle_lib, width):
         for t in range(k):
             z = sum(int(T[t][q]) * int(hcount[q]) for q in range(e)) * (a_ * b_) & M64
             assert int(out[t]) == ((z & 0xFFFFFFFF) * (z >> 32)) & M64, (c, u, j, t)
+
+
+# ---------------------------------------------------------------------------
+# Composition with simple tabulation (§1: a universe-collapsing family feeds
+# a short-input family; §7: pairing with a fast short-input family).
+# ---------------------------------------------------------------------------
+
+def _identity_window(width, m):
+    """Tables whose XOR over a key is the little-endian word of key bytes
+    8m .. 8m+7: T_i[v] = v << 8(i - 8m) inside the window, zero elsewhere."""
+    t = np.zeros((width + 1, 256), dtype=np.uint64)
+    for i in range(8 * m, 8 * m + 8):
+        t[i] = np.arange(256, dtype=np.uint64) << np.uint64(8 * (i - 8 * m))
+    return t
+
+
+@pytest.mark.parametrize("b", [8, 4])
+@pytest.mark.parametrize("width", WIDTHS)
+def test_hash64_identity_tables_reproduce_key_bytes(oracle_lib, width, b):
+    """With identity tables on window m the result is word m of the key: of
+    the zero-padded string itself for L <= c, of its HalftimeHash value (inner
+    width c, block size b) for L > c."""
+    o = oracle_lib
+    ent = o.expand_seed(9, b=b)
+    for L in (0, 1, 7, 8, width - 1, width, width + 1, 1000, 3000):
+        x = wl.random_bytes(L + 1, L)
+        for m in range(width // 8):
+            z = o.hash64(ent, _identity_window(width, m), x, width, b=b)
+            if L <= width:
+                key = np.zeros(width, dtype=np.uint8)
+                key[:L] = x
+            else:
+                key = o.hash_bytes(ent, x, width, b=b)
+            assert z == int(key[8 * m:8 * m + 8].view("<u8")[0]), (L, m)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_hash64_separator_character(oracle_lib, width):
+    """Only the last table non-zero, T_c[v] = v: the result is the separator
+    character, L for strings of at most c bytes and 255 for longer ones."""
+    o = oracle_lib
+    ent = o.expand_seed(9)
+    t = np.zeros((width + 1, 256), dtype=np.uint64)
+    t[width] = np.arange(256, dtype=np.uint64)
+    for L in list(range(0, width + 3)) + [500, 2000]:
+        assert o.hash64(ent, t, wl.random_bytes(L, L), width) == (L if L <= width else 255)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_hash64_is_xor_of_table_entries(oracle_lib, width):
+    """The result is linear over XOR in the tables (and not over addition),
+    two keys that differ in one character differ by exactly the two table
+    entries of that character, and the empty string gives the XOR of every
+    table's entry 0 with T_c[0]."""
+    o = oracle_lib
+    ent = o.expand_seed(10)
+    t1, t2 = o.tab_expand(1, width), o.tab_expand(2, width)
+    for L in (0, 3, width, width + 1, 1500):
+        x = wl.random_bytes(L + 7, L)
+        z1, z2 = o.hash64(ent, t1, x, width), o.hash64(ent, t2, x, width)
+        assert o.hash64(ent, t1 ^ t2, x, width) == z1 ^ z2
+        assert o.hash64(ent, t1 ^ t2, x, width) != (z1 + z2) & M64
+    rng = np.random.default_rng(width)
+    for _ in range(50):
+        L = int(rng.integers(1, width + 1))
+        j = int(rng.integers(0, L))
+        x = rng.integers(0, 256, L).astype(np.uint8)
+        y = x.copy()
+        y[j] ^= np.uint8(rng.integers(1, 256))
+        d = o.hash64(ent, t1, x, width) ^ o.hash64(ent, t1, y, width)
+        assert d == int(t1[j, x[j]]) ^ int(t1[j, y[j]])
+    expect = 0
+    for i in range(width):
+        expect ^= int(t1[i, 0])
+    assert o.hash64(ent, t1, b"", width) == expect ^ int(t1[width, 0])
+
+
+def test_hash64_short_keys_do_not_collide(oracle_lib):
+    """Simple tabulation is 3-independent, so two distinct keys collide with
+    probability 2^-64: none among all strings of at most two bytes (65,793
+    keys), nor between them and 2,000 longer strings."""
+    o = oracle_lib
+    width = 16
+    ent = o.expand_seed(11)
+    t = o.tab_expand(12, width)
+    keys = [b""] + [bytes([a]) for a in range(256)] + [bytes([a, c]) for a in range(256) for c in range(256)]
+    lens = np.array([len(k) for k in keys] + [17 + i for i in range(2000)], dtype=np.uint64)
+    data = np.concatenate([np.frombuffer(b"".join(keys), dtype=np.uint8), wl.random_bytes(13, int(lens[len(keys):].sum()))])
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    z = o.hash64_batch(ent, t, data, offs, lens, width, nthreads=8)
+    assert np.unique(z).size == z.size
+    # the batch routine agrees with the single-string one
+    for i in (0, 1, 300, 65792, 65793, z.size - 1):
+        assert int(z[i]) == o.hash64(ent, t, data[int(offs[i]):int(offs[i] + lens[i])], width)
+
+
+def test_tab_expand_is_splitmix64(oracle_lib):
+    """The tables are the first (c + 1) * 256 outputs of splitmix64 from the
+    user seed: the same stream the entropy expansion is pinned to."""
+    o = oracle_lib
+    for width in WIDTHS:
+        t = o.tab_expand(77, width)
+        assert t.shape == (width + 1, 256) and o.tab_words(width) == (width + 1) * 256
+        assert (t.ravel() == o.expand_seed(77)[:t.size]).all()
+    with pytest.raises(ValueError):
+        o.tab_words(20)
