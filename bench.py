@@ -130,7 +130,7 @@ def run_main():
     ap.add_argument("--cpu-sample", type=int, default=1024, help="oracle strings per width")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
-    ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve"), default="throughput")
+    ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve", "compose"), default="throughput")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per offered load (serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
     ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default launch choice")
@@ -152,6 +152,8 @@ def run_main():
         line = run_long(args)
     elif args.workload == "serve":
         line = run_serve(args)
+    elif args.workload == "compose":
+        line = run_compose(args)
     else:
         line = run_throughput(args)
     print(json.dumps(line), flush=True)
@@ -566,6 +568,110 @@ def run_long(args):
         "roofline": _roofline(f"hth::hash_main_kernel<{width}, 8, false>", algo, kernel_ms),
         "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
         "streaming": streaming,
+        "cpu_baseline": cpu,
+    }
+
+
+def _event_ms(torch, launch, steps):
+    """Average ms of `launch` over `steps` calls, by events on the current stream."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        launch()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def run_compose(args):
+    """The composed 64-bit hash (HalftimeHash + simple tabulation), inner
+    width 16: 16,777,216 hash-table keys of 0..64 bytes (lengths uniform,
+    bytes from splitmix64 seed 7, packed back to back), then the uneven batch."""
+    import torch
+    from paper_2104_08865_amd import hth
+    from paper_2104_08865_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    width = 16
+    seed = hth.expand_seed(7)
+    tables = hth.tab_tables(8, width)
+
+    # short keys
+    lens = wl.short_key_lengths()
+    offs, total = wl.pack(lens)
+    count = lens.size
+    log(f"[bench] compose: {count} keys, {total} bytes")
+    data = wl.random_bytes_torch(7, total, dev)
+    o = torch.from_numpy(offs.view(np.int64)).to(dev)
+    n = torch.from_numpy(lens.view(np.int64)).to(dev)
+    hth.reserve(count)
+    z = torch.empty(count, dtype=torch.int64, device=dev)
+    h = torch.empty((count, width), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        hth.hash_batch64(seed, tables, data, o, n, width, out=z)
+        hth.hash_batch(seed, data, o, n, width, out=h)
+    wall = _timed_launches(hth, torch, lambda: hth.hash_batch64(seed, tables, data, o, n, width, out=z), args.steps)
+    ms64 = _event_ms(torch, lambda: hth.hash_batch64(seed, tables, data, o, n, width, out=z), args.steps)
+    ms16 = _event_ms(torch, lambda: hth.hash_batch(seed, data, o, n, width, out=h), args.steps)
+    hth.batch_check()
+    keys_per_s = count * args.steps / wall
+    # algorithmic bytes of one call: offset, length and result of every key,
+    # the bytes of the short keys, the HalftimeHash input of the longer ones
+    # plus their 16-byte values written and read back
+    long_ = lens > width
+    algo = int(count * 24 + total + int(long_.sum()) * 2 * width)
+    log(f"[bench] composed: {keys_per_s / 1e6:.0f} M keys/s ({ms64:.3f} ms per call); "
+        f"HalftimeHash alone (16-byte values): {ms16:.3f} ms per call")
+    zs = z.cpu().numpy().view(np.uint64)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ent = oracle.expand_seed(7)
+        tab = oracle.tab_expand(8, width)
+        m = 1 << 20
+        sub = data[:int(offs[m - 1] + lens[m - 1])].cpu().numpy()
+        ref, dt, core = pinned_oracle(lambda: oracle.hash64_batch(ent, tab, sub, offs[:m], lens[:m], width))
+        cpu = {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {m} of the {count} keys, single thread pinned to core {core}",
+               "seconds": dt, "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
+               "bit_exact_vs_gpu": bool((zs[:m] == ref).all())}
+        log(f"[bench] cpu oracle: {m / dt / 1e6:.2f} M keys/s, exact={cpu['bit_exact_vs_gpu']}")
+    del data, o, n, z, h
+    torch.cuda.empty_cache()
+
+    # the uneven batch, composed and as plain 16-byte values
+    ulens = wl.uneven_lengths(3)
+    uoffs, utotal = wl.pack(ulens)
+    udata = wl.random_bytes_torch(3, utotal, dev)
+    uo = torch.from_numpy(uoffs.view(np.int64)).to(dev)
+    un = torch.from_numpy(ulens.view(np.int64)).to(dev)
+    uz = torch.empty(ulens.size, dtype=torch.int64, device=dev)
+    uh = torch.empty((ulens.size, width), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        hth.hash_batch64(seed, tables, udata, uo, un, width, out=uz)
+        hth.hash_batch(seed, udata, uo, un, width, out=uh)
+    ums64 = _event_ms(torch, lambda: hth.hash_batch64(seed, tables, udata, uo, un, width, out=uz), args.steps)
+    ums16 = _event_ms(torch, lambda: hth.hash_batch(seed, udata, uo, un, width, out=uh), args.steps)
+    hth.batch_check()
+    log(f"[bench] uneven batch composed: {utotal / ums64 / 1e6:.0f} GB/s; 16-byte values: {utotal / ums16 / 1e6:.0f} GB/s")
+    del udata
+
+    return {
+        "metric": "composed 64-bit hash (HalftimeHash + simple tabulation) keys/s",
+        "value": keys_per_s, "unit": "keys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "16,777,216 keys of 0..64 bytes (uniform lengths, splitmix64 seed 7), "
+                               "inner width 16, tables from splitmix64 seed 8",
+                   "keys": count, "key_bytes": total, "inner_width": width},
+        "roofline": _roofline("whole hth_hash_batch64 call (planner, hashing, tail-only and tabulation kernels)",
+                              algo, ms64),
+        "plain_hash_batch_width16_ms": ms16,
+        "uneven_batch": {"strings": int(ulens.size), "bytes": utotal, "composed_GBps": utotal / ums64 / 1e6,
+                         "values16_GBps": utotal / ums16 / 1e6, "composed_ms": ums64, "values16_ms": ums16},
         "cpu_baseline": cpu,
     }
 

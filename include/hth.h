@@ -143,6 +143,50 @@ hth_status hth_hash_batch_timed(const hth_seed *seed, const uint8_t *bytes, cons
                                 hipEvent_t main_stop);
 
 /* ------------------------------------------------------------------------ */
+/* Composition with a short-input family (§1: a universe-collapsing family   */
+/* reduces each long string to a few bytes, which a short-input family then  */
+/* hashes as if they were the input; §7 names pairing HalftimeHash with a    */
+/* fast short-input family as future work).                                  */
+/* ------------------------------------------------------------------------ */
+
+/* The short-input family is simple tabulation over c + 1 byte characters,
+   c = inner_width (16, 24, 32 or 40), with one table of 256 random 64-bit
+   words per character: tables[i * 256 + v] = T_i[v], i = 0 .. c.  The key of
+   a string x of L bytes is
+     L <= c:  characters 0 .. c-1 = x zero-padded to c bytes, character c = L
+              (the string is tabulated directly: no HalftimeHash work);
+     L >  c:  characters 0 .. c-1 = the c-byte HalftimeHash value of x
+              (hth_hash_batch with out_width c), character c = 255;
+   and the 64-bit result is the XOR of T_i[character i] over i = 0 .. c.
+   Keys of the two kinds always differ in character c, and simple tabulation
+   makes any two distinct keys collide with probability 2^-64, so two
+   distinct strings collide with probability at most eps_c + 2^-64 (eps_c of
+   the inner width's family, §6.2).
+
+   Words of the tables for inner width c: (c + 1) * 256, 0 for another width. */
+size_t hth_tab_words(uint32_t inner_width);
+
+/* Fill host memory `words` (n_words must equal hth_tab_words(inner_width))
+   with tables: word i = output i of splitmix64 started at user_seed (the
+   generator of hth_expand_seed; pick a user seed independent of the hashing
+   seed's).  Errors: HTH_E_INVALID. */
+hth_status hth_tab_expand(uint64_t user_seed, uint32_t inner_width, uint64_t *words, size_t n_words);
+
+/* The composed 64-bit hash of `count` strings.  Arguments as hth_hash_batch,
+   and:
+     tables  device pointer, hth_tab_words(inner_width) words, 8-byte aligned,
+             owned by the caller (valid until `stream` reaches this work);
+     out     device pointer to count uint64_t, 8-byte aligned.
+   Enqueues the planner and hashing kernels of hth_hash_batch for the strings
+   longer than inner_width bytes (their values go to the stream's workspace),
+   then one tabulation kernel for every string, on `stream`.  Same workspace
+   rules as hth_hash_batch.  Errors: HTH_E_INVALID (as hth_hash_batch, null
+   or misaligned tables/out with count > 0), HTH_E_OOM, HTH_E_HIP. */
+hth_status hth_hash_batch64(const hth_seed *seed, const uint64_t *tables, const uint8_t *bytes,
+                            const uint64_t *offsets, const uint64_t *lengths, uint64_t count, uint64_t *out,
+                            uint32_t inner_width, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Captured batches (HIP graphs).                                            */
 /* ------------------------------------------------------------------------ */
 

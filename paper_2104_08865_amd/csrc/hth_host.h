@@ -27,6 +27,7 @@ struct Workspace {
   size_t bytes = 0;
   uint32_t* ctl = nullptr;
   uint64_t* block_sums = nullptr;
+  uint64_t* block_pre = nullptr;
   uint32_t* task_string = nullptr;
   uint32_t* task_start = nullptr;
   uint32_t* acc_start = nullptr;
@@ -36,6 +37,7 @@ struct Workspace {
   uint32_t* sdone = nullptr;
   uint64_t* gacc = nullptr;
   uint32_t* gcnt = nullptr;
+  uint8_t* hbuf = nullptr;  // [cap_count][40]: inner values of the composed 64-bit hash
 };
 
 // Error reporting: sets the thread's hth_last_error message, returns code.
@@ -47,6 +49,13 @@ bool width_ok(uint32_t w);
 // is freed after `stream` drains.
 hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream);
 
+// Workspace for (current device, stream) with room for `count` strings
+// (grown on the host; refused inside a stream capture).
+hth_status get_ws(uint64_t count, hipStream_t stream, Workspace** out);
+
+// splitmix64 outputs 1 .. n from `state` (the generator of the seed expansion).
+void splitmix64_fill(uint64_t state, uint64_t* out, size_t n);
+
 // Validates the arguments of one batch (as hth_hash_batch).
 hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                             const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width);
@@ -57,11 +66,12 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 // knows the lengths on the host passes an upper bound of the batch's tasks.
 // roots, when non-null, selects root mode (every string a block of exactly
 // 8^L executions; its root node, kMaxK x 8 words, goes to roots[i]; out
-// is not written).
+// is not written).  Strings shorter than direct_lim bytes are not hashed
+// (their rows of out are not written).
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
                          hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0,
-                         uint64_t* roots = nullptr);
+                         uint64_t* roots = nullptr, uint32_t direct_lim = 0);
 
 // Upper bound of the tasks a string of `len` bytes can make (at the finest
 // task size) in the family with `block` words per block, for max_waves.

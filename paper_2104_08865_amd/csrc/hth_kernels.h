@@ -23,8 +23,12 @@ constexpr int kPlanSums = 3;  // per candidate task size: tasks, accumulators, w
 // Per planner block: kPlanSums per candidate, then the block's tail-only strings.
 constexpr int kBlockSums = kPlanCandidates * kPlanSums + 1;
 // Tail-only strings (shorter than one EHC execution) get no task: they are
-// listed apart and hashed one string per lane, kTinyChunk strings per fetch.
+// listed apart and hashed one string per lane, in chunks of kTinyChunk
+// strings; wave w of the tail-only kernel takes chunks w, w + grid, ...
 constexpr int kTinyChunk = 64;
+// Plans of more planner blocks than this get the scan kernel between their
+// two steps (linear in the block count); smaller ones sum in the fill step.
+constexpr uint32_t kPlanScanMin = 256;
 
 // Control words of one launch (device memory, written by the planner).
 enum {
@@ -34,7 +38,8 @@ enum {
   kCtlError,
   kCtlBuckets,   // number of buckets (leaders)
   kCtlTiny,      // number of tail-only strings
-  kCtlTinyNext,  // next chunk of tail-only strings to hand out
+  kCtlBucketLo,  // bucket size in work bytes (low, high word), for the fill step
+  kCtlBucketHi,
   kCtlWords = 16
 };
 
@@ -43,7 +48,9 @@ struct PlanArgs {
   uint64_t count;
   uint32_t exec_bytes;
   uint32_t pass_log2;     // log2 of the executions of one pass (7 for b = 8, 8 for b = 4)
+  uint32_t direct_lim;    // strings shorter than this are not hashed at all (0: every string is)
   uint64_t* block_sums;  // [nblocks][kBlockSums]
+  uint64_t* block_pre;   // [nblocks][kPlanSums + 1]: per-block prefixes (large plans)
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
@@ -84,8 +91,27 @@ uint64_t plan_block_count(uint64_t count);
 // Reads n16 16-byte pieces of buf; sink holds `blocks` words (XOR-folded).
 hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint32_t blocks, hipStream_t stream);
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
-// The hashing kernel, then the tail-only kernel, both with `grid` waves.
-hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
+// The hashing kernel with `grid` waves, then the tail-only kernel with
+// `tiny_grid` waves.
+hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, uint32_t tiny_grid,
+                       hipStream_t stream);
+const void* tiny_kernel_fn(uint32_t width, uint32_t block);
+
+// Composition with simple tabulation: one string per thread; the string's
+// key is its own bytes (lengths <= width) or its HalftimeHash value in h.
+struct TabArgs {
+  const uint8_t* bytes;
+  const uint64_t* offsets;
+  const uint64_t* lengths;
+  uint64_t count;
+  const uint8_t* h;        // [count][width]: values of the strings longer than width bytes
+  const uint64_t* tables;  // [(width + 1) * 256]
+  uint64_t* out;           // [count]
+};
+hipError_t launch_tab(uint32_t width, const TabArgs& a, uint32_t grid, hipStream_t stream);
+const void* tab_kernel_fn(uint32_t width);
+// Threads of one tabulation workgroup.
+constexpr int kTabThreads = 1024;
 
 // Streaming.  Root mode: every string is a block of exactly 8^L executions
 // whose root node (kMaxK x 8 words, [t][j]) goes to a.roots; no tail-only

@@ -196,7 +196,9 @@ __device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_e
 // Per string and per candidate task size 2^pass_log2 * 8^j executions (a
 // pass is 128 executions for b = 8, 256 for b = 4): number of tasks, and
 // number of cross-task accumulators (complete nodes of levels >= j + 3).
-// A tail-only string (N = 0) has no task: it is hashed from the tiny list.
+// A tail-only string (N = 0) has no task: it is hashed from the tiny list,
+// unless it is shorter than the planner's direct_lim (the composed 64-bit
+// hash tabulates such strings itself; direct_lim is 0 for every other caller).
 __device__ __forceinline__ void plan_counts(uint64_t N, int j, uint32_t pass_log2, uint64_t& tasks,
                                             uint64_t& accs) {
   const int shift = (int)pass_log2 + 3 * j;
@@ -259,8 +261,8 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
 // Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
 // accumulators and work of its kPlanBlock strings.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
-                                uint32_t exec_bytes, uint32_t pass_log2, uint64_t* __restrict__ block_sums,
-                                uint32_t* __restrict__ ctl) {
+                                uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim,
+                                uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves][kBlockSums];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
@@ -283,7 +285,7 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     v[j * kPlanSums + 2] = w;
   }
   uint64_t tiny = 0;
-  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && L[i] < exec_bytes;
+  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && L[i] < exec_bytes && L[i] >= direct_lim;
   v[kBlockSums - 1] = tiny;
   block_sum_n(v, lds);
   if (threadIdx.x < kBlockSums) {
@@ -294,25 +296,12 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
   }
 }
 
-// Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
-__device__ void plan_fill_body(
-    uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
-    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
-    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
-    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t lds[kPlanWaves];
-  __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
-  __shared__ uint64_t lds4[kPlanWaves][kPlanSums + 1];
-  __shared__ uint32_t incl[kPlanBlock];
-  __shared__ uint64_t wstart[kPlanBlock];
-  const int tid = threadIdx.x;
-  // Totals of every candidate over all blocks (threads stride over blocks).
-  uint64_t tot[kBlockSums];
-  for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
-  for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
-    for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
-  block_sum_n(tot, ldsn);
+// Task level and bucket size from the totals over every planner block;
+// `write_ctl`: this thread also writes the launch's control words.  jsel < 0
+// means that no task level fits the workspace (the launch does nothing).
+__device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_tasks, uint64_t cap_accs,
+                            uint32_t min_j, uint32_t max_j, uint64_t target_tasks, bool write_ctl,
+                            uint32_t* __restrict__ ctl, int& jsel_out, uint64_t& bucket_out) {
   uint64_t tt[kPlanCandidates], ta[kPlanCandidates], tw[kPlanCandidates];
   for (int j = 0; j < kPlanCandidates; ++j) {
     tt[j] = tot[j * kPlanSums + 0];
@@ -332,22 +321,61 @@ __device__ void plan_fill_body(
   const uint64_t total_work = jsel >= 0 ? tw[jsel] : 0;
   uint64_t bucket = (total_work + kMaxBuckets - 1) / kMaxBuckets;
   if (bucket < kMinBucketBytes) bucket = kMinBucketBytes;
-  if (blk == 0 && tid == 0) {
+  if (write_ctl) {
     ctl[kCtlNext] = 0;
     ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
     ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
     ctl[kCtlError] = jsel >= 0 ? 0 : 1;
     ctl[kCtlTiny] = jsel >= 0 ? (uint32_t)tot[kBlockSums - 1] : 0;
-    ctl[kCtlTinyNext] = 0;
+    ctl[kCtlBucketLo] = (uint32_t)bucket;
+    ctl[kCtlBucketHi] = (uint32_t)(bucket >> 32);
   }
-  if (jsel < 0) return;  // uniform over the grid
-  // Tasks, accumulators, work and tail-only strings of the blocks before this one.
+  jsel_out = jsel;
+  bucket_out = bucket;
+}
+
+// Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
+// Without block_pre, the workgroup sums the other blocks' step-1 results
+// itself (cost grows with the square of the block count: small plans);
+// with it, the scan kernel has chosen the task level and bucket size (control
+// words) and written each block's prefix (block_pre[blk]).
+__device__ void plan_fill_body(
+    uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
+    uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
+    const uint64_t* __restrict__ block_pre, uint64_t cap_tasks, uint64_t cap_accs,
+    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
+    uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
+    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
+  __shared__ uint64_t lds[kPlanWaves];
+  __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
+  __shared__ uint64_t lds4[kPlanWaves][kPlanSums + 1];
+  __shared__ uint32_t incl[kPlanBlock];
+  __shared__ uint64_t wstart[kPlanBlock];
+  const int tid = threadIdx.x;
+  int jsel;
+  uint64_t bucket;
   uint64_t pre[kPlanSums + 1] = {0, 0, 0, 0};
-  for (uint32_t b = tid; b < blk; b += kPlanThreads) {
-    for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)b * kBlockSums + jsel * kPlanSums + k];
-    pre[kPlanSums] += block_sums[(uint64_t)b * kBlockSums + kBlockSums - 1];
+  if (block_pre) {
+    jsel = ctl[kCtlError] ? -1 : (int)ctl[kCtlLevel];
+    bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
+    if (jsel < 0) return;  // uniform over the grid
+    for (int k = 0; k <= kPlanSums; ++k) pre[k] = block_pre[(uint64_t)blk * (kPlanSums + 1) + k];
+  } else {
+    // Totals of every candidate over all blocks (threads stride over blocks).
+    uint64_t tot[kBlockSums];
+    for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
+    for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
+      for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
+    block_sum_n(tot, ldsn);
+    plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, blk == 0 && tid == 0, ctl, jsel, bucket);
+    if (jsel < 0) return;  // uniform over the grid
+    // Tasks, accumulators, work and tail-only strings of the blocks before this one.
+    for (uint32_t b = tid; b < blk; b += kPlanThreads) {
+      for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)b * kBlockSums + jsel * kPlanSums + k];
+      pre[kPlanSums] += block_sums[(uint64_t)b * kBlockSums + kBlockSums - 1];
+    }
+    block_sum_n(pre, lds4);
   }
-  block_sum_n(pre, lds4);
   const uint64_t task_base = pre[0];
   const uint64_t acc_base = pre[1];
   const uint64_t work_base = pre[2];
@@ -364,7 +392,7 @@ __device__ void plan_fill_body(
       const uint64_t L = lengths[base + i];
       plan_counts(L / exec_bytes, jsel, pass_log2, tk[i], ac[i]);
       wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
-      tiny[i] = L < exec_bytes;
+      tiny[i] = L < exec_bytes && L >= direct_lim;
     }
     st += tk[i];
     sa += ac[i];
@@ -438,19 +466,60 @@ __device__ void plan_fill_body(
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
                                                                   uint64_t count, uint32_t exec_bytes,
-                                                                  uint32_t pass_log2,
+                                                                  uint32_t pass_log2, uint32_t direct_lim,
                                                                   uint64_t* __restrict__ block_sums,
                                                                   uint32_t* __restrict__ ctl) {
-  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, block_sums, ctl);
+  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl);
+}
+
+// Large plans, between the two steps: totals, the task level and bucket
+// size (control words), and every block's exclusive prefix of tasks,
+// accumulators, work and tail-only strings at that level, in one workgroup
+// (linear in the block count).  Thread t owns a contiguous run of blocks.
+__global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(
+    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
+    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint64_t* __restrict__ block_pre,
+    uint32_t* __restrict__ ctl) {
+  __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
+  __shared__ uint64_t lds[kPlanWaves];
+  const int tid = threadIdx.x;
+  uint64_t tot[kBlockSums];
+  for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
+  for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
+    for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
+  block_sum_n(tot, ldsn);
+  int jsel;
+  uint64_t bucket;
+  plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, tid == 0, ctl, jsel, bucket);
+  if (jsel < 0) return;  // uniform over the workgroup
+  constexpr int NP = kPlanSums + 1;
+  const uint32_t per = (nblocks + kPlanThreads - 1) / kPlanThreads;
+  const uint32_t b0 = tid * per < nblocks ? tid * per : nblocks;
+  const uint32_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
+  auto value = [&](uint32_t b, int k) {
+    return block_sums[(uint64_t)b * kBlockSums + (k < kPlanSums ? jsel * kPlanSums + k : kBlockSums - 1)];
+  };
+  uint64_t run[NP];
+  for (int k = 0; k < NP; ++k) {
+    uint64_t mine = 0, total = 0;
+    for (uint32_t b = b0; b < b1; ++b) mine += value(b, k);
+    run[k] = block_exclusive(mine, lds, total);
+  }
+  for (uint32_t b = b0; b < b1; ++b)
+    for (int k = 0; k < NP; ++k) {
+      block_pre[(uint64_t)b * NP + k] = run[k];
+      run[k] += value(b, k);
+    }
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
+    uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
+    const uint64_t* __restrict__ block_pre, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, block_sums, nblocks, cap_tasks, cap_accs, min_j, max_j,
+  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, nblocks, block_pre, cap_tasks, cap_accs, min_j, max_j,
                  target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -459,13 +528,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
 // step 1's global writes visible to the whole workgroup.
 __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    uint64_t* __restrict__ block_sums, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
+    uint32_t direct_lim, uint64_t* __restrict__ block_sums, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
     uint64_t target_tasks,
     uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
     uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_count_body(0, lengths, count, exec_bytes, pass_log2, block_sums, ctl);
+  plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl);
   __syncthreads();
-  plan_fill_body(0, lengths, count, exec_bytes, pass_log2, block_sums, 1, cap_tasks, cap_accs, min_j, max_j, target_tasks,
+  plan_fill_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, 1, nullptr, cap_tasks, cap_accs, min_j, max_j, target_tasks,
                  task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -760,18 +829,30 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
 #pragma unroll
       for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[c], ent[Ly::tail + t + m + c]);
   }
-  // remaining whole words, then the zero-padded last word
-  for (; 8 * m + 8 <= L; ++m) {
-    uint64_t w;
-    __builtin_memcpy(&w, str + 8 * m, 8);
+  // the rest (under 128 bytes): up to 15 whole words and a zero-padded last
+  // word, every load issued before the first is used
+  const uint64_t rem = L - 8 * m;
+  const uint32_t nw = (uint32_t)(rem / 8), nb = (uint32_t)(rem % 8);
+  const uint8_t* __restrict__ rp = str + 8 * m;
+  uint64_t w[15];
 #pragma unroll
-    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+  for (int j = 0; j < 15; ++j) {
+    w[j] = 0;
+    if ((uint32_t)j < nw) __builtin_memcpy(&w[j], rp + 8 * j, 8);
   }
-  if (L & 7) {
-    uint64_t w = 0;
-    for (uint64_t b = 0; b < (L & 7); ++b) w |= (uint64_t)str[8 * m + b] << (8 * b);
+  uint64_t last = 0;
 #pragma unroll
-    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+  for (int b = 0; b < 7; ++b)
+    if ((uint32_t)b < nb) last |= (uint64_t)rp[8 * nw + b] << (8 * b);
+#pragma unroll
+  for (int j = 0; j < 15; ++j)
+    if ((uint32_t)j < nw) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[j], ent[Ly::tail + t + m + j]);
+    }
+  if (nb) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], last, ent[Ly::tail + t + m + nw]);
   }
   uint8_t* o = a.out + (uint64_t)s * WIDTH;
 #pragma unroll
@@ -782,26 +863,18 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
 }
 
 // Tail-only strings (shorter than one execution: §6.1's tail and the length
-// term, no tree), one string per lane, in chunks of kTinyChunk strings taken
-// from a device counter.  A separate kernel: inside the hashing kernel this
-// code cost the full passes 3-10 % (register allocation of the whole
-// kernel), while a launch costs a few microseconds.
+// term, no tree), one string per lane, in chunks of kTinyChunk strings: wave
+// w takes chunks w, w + grid, ...  A tail-only string costs at most a few
+// dozen loads, so static shares balance, and no wave queues on a counter (one
+// device atomic per chunk serialised millions of short strings).  A separate
+// kernel: inside the hashing kernel this code cost the full passes 3-10 %
+// (register allocation of the whole kernel), while a launch costs a few
+// microseconds.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
-  const int lane = threadIdx.x;
   const uint32_t ntiny = uniform(a.ctl[kCtlTiny]);
-  const uint32_t nchunks = (ntiny + kTinyChunk - 1) / kTinyChunk;
-  // most waves of a grid larger than the work leave on a plain read
-  uint32_t seen = 0;
-  if (lane == 0) seen = __hip_atomic_load(a.ctl + kCtlTinyNext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (uniform(seen) >= nchunks) return;
-  for (;;) {
-    __builtin_amdgcn_wave_barrier();
-    uint32_t k = 0;
-    if (lane == 0) k = atomicAdd(a.ctl + kCtlTinyNext, 1u);
-    k = uniform(k);
-    if (k >= nchunks) return;
-    const uint32_t idx = k * kTinyChunk + (uint32_t)lane;
+  for (uint32_t k = blockIdx.x; (uint64_t)k * kTinyChunk < ntiny; k += gridDim.x) {
+    const uint32_t idx = k * kTinyChunk + threadIdx.x;
     if (idx < ntiny) tiny_one<WIDTH, B>(a, a.tiny_list[idx]);
   }
 }
@@ -1260,6 +1333,12 @@ const void* main_kernel_fn(uint32_t width, uint32_t block) {
   return f;
 }
 
+const void* tiny_kernel_fn(uint32_t width, uint32_t block) {
+  const void* f = nullptr;
+  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&tiny_kernel<W, Bk>));
+  return f;
+}
+
 uint32_t exec_bytes_of(uint32_t width, uint32_t block) {
   uint32_t x = 0;
   HTH_DISPATCH(width, block, x = Layout<W, Bk>::exec_bytes);
@@ -1277,28 +1356,37 @@ uint64_t entropy_words_total(uint32_t block) {
 
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const uint32_t nblocks = (uint32_t)((p.count + kPlanBlock - 1) / kPlanBlock);
+  const bool scan = nblocks > kPlanScanMin;
   if (nblocks == 1) {
     hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
-                       p.pass_log2, p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
+                       p.pass_log2, p.direct_lim, p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
                        p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.pass_log2, p.block_sums, p.ctl);
+                     p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, p.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (scan) {
+    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.block_sums, nblocks, p.cap_tasks,
+                       p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.block_pre, p.ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.pass_log2, p.block_sums, nblocks, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
+                     p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks,
+                     scan ? (const uint64_t*)p.block_pre : nullptr, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
                      p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream) {
+hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, uint32_t tiny_grid,
+                       hipStream_t stream) {
   // the hashing kernel, then the tail-only strings
   bool known = false;
   HTH_DISPATCH(width, block, {
     hipLaunchKernelGGL((hash_main_kernel<W, Bk, false>), dim3(grid), dim3(64), 0, stream, a);
-    hipLaunchKernelGGL((tiny_kernel<W, Bk>), dim3(grid), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((tiny_kernel<W, Bk>), dim3(tiny_grid), dim3(64), 0, stream, a);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;

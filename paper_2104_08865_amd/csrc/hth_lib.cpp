@@ -69,6 +69,11 @@ std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 Tuning g_tune[4];
 std::map<std::pair<int, int>, uint32_t> g_grid;  // (device, width index + 4 for b = 4) -> persistent grid
+std::map<std::pair<int, int>, uint32_t> g_tiny_grid;  // same keys -> resident tail-only waves
+
+// Resident waves per compute unit of the tail-only kernel: it is light on
+// registers and latency-bound, so it runs deeper than the hashing kernel.
+constexpr uint32_t kTinyWavesPerCU = 16;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -87,6 +92,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   };
   size_t o_ctl = take(hth::kCtlWords * 4);
   size_t o_bs = take(n.cap_blocks * hth::kBlockSums * 8);
+  size_t o_bp = take(n.cap_blocks * (hth::kPlanSums + 1) * 8);
   size_t o_ts = take(n.cap_tasks * 4);
   size_t o_st = take(n.cap_count * 4);
   size_t o_as = take(n.cap_count * 4);
@@ -96,6 +102,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   size_t o_sdone = take(n.cap_count * 4);
   size_t o_gacc = take(n.cap_accs * hth::kMaxK * 8 * 8);
   size_t o_gcnt = take(n.cap_accs * 4);
+  size_t o_h = take(n.cap_count * 40);
   n.bytes = off;
   hipError_t e = hipMalloc(&n.mem, n.bytes);
   if (e != hipSuccess) return hip_fail(e, "workspace allocation");
@@ -108,6 +115,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   char* b = static_cast<char*>(n.mem);
   n.ctl = reinterpret_cast<uint32_t*>(b + o_ctl);
   n.block_sums = reinterpret_cast<uint64_t*>(b + o_bs);
+  n.block_pre = reinterpret_cast<uint64_t*>(b + o_bp);
   n.task_string = reinterpret_cast<uint32_t*>(b + o_ts);
   n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
   n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
@@ -117,6 +125,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   n.sdone = reinterpret_cast<uint32_t*>(b + o_sdone);
   n.gacc = reinterpret_cast<uint64_t*>(b + o_gacc);
   n.gcnt = reinterpret_cast<uint32_t*>(b + o_gcnt);
+  n.hbuf = reinterpret_cast<uint8_t*>(b + o_h);
   if (w.mem) {
     // the old workspace may still be in use by work queued on this stream
     e = hipStreamSynchronize(stream);
@@ -177,6 +186,36 @@ hth_status grid_for(uint32_t width, uint32_t block, uint32_t* grid) {
   return HTH_OK;
 }
 
+// Waves of the tail-only kernel for a batch of `count` strings: resident
+// waves up to kTinyWavesPerCU per CU, and no more than its chunks.
+hth_status tiny_grid_for(uint32_t width, uint32_t block, uint64_t count, uint32_t* grid) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  uint32_t full = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int key = width_index(width) + (block == 4 ? 4 : 0);
+    auto it = g_tiny_grid.find({dev, key});
+    if (it != g_tiny_grid.end()) {
+      full = it->second;
+    } else {
+      int cus = 0, per_cu = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::tiny_kernel_fn(width, block), 64, 0);
+      if (e != hipSuccess) return hip_fail(e, "tail-only kernel occupancy query");
+      uint32_t wpc = per_cu > 0 ? (uint32_t)per_cu : 1;
+      if (wpc > kTinyWavesPerCU) wpc = kTinyWavesPerCU;
+      full = (uint32_t)cus * wpc;
+      g_tiny_grid[{dev, key}] = full;
+    }
+  }
+  const uint64_t chunks = (count + hth::kTinyChunk - 1) / hth::kTinyChunk;
+  *grid = chunks < full ? (uint32_t)(chunks ? chunks : 1) : full;
+  return HTH_OK;
+}
+
 }  // namespace host
 }  // namespace hth
 
@@ -207,7 +246,7 @@ hth_status check_batch_args(const hth_seed* seed, const uint8_t* bytes, const ui
 hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint64_t* offsets,
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
                          hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves,
-                         uint64_t* roots) {
+                         uint64_t* roots, uint32_t direct_lim) {
   const uint32_t block = seed->block;
   uint32_t grid = 0;
   hth_status st = grid_for(out_width, block, &grid);
@@ -223,7 +262,9 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   p.count = count;
   p.exec_bytes = hth::exec_bytes_of(out_width, block);
   p.pass_log2 = hth::pass_log2_of(block);
+  p.direct_lim = direct_lim;
   p.block_sums = w.block_sums;
+  p.block_pre = w.block_pre;
   p.cap_tasks = w.cap_tasks;
   p.cap_accs = w.cap_accs;
   p.min_j = tune.min_j;
@@ -256,7 +297,13 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.roots = roots;
   a.ctl = w.ctl;
   if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
-  e = roots ? hth::launch_roots(out_width, block, a, grid, stream) : hth::launch_main(out_width, block, a, grid, stream);
+  uint32_t tiny_grid = 1;
+  if (!roots) {
+    st = tiny_grid_for(out_width, block, count, &tiny_grid);
+    if (st != HTH_OK) return st;
+  }
+  e = roots ? hth::launch_roots(out_width, block, a, grid, stream)
+            : hth::launch_main(out_width, block, a, grid, tiny_grid, stream);
   if (e != hipSuccess) return hip_fail(e, "main launch");
   if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;
@@ -410,7 +457,8 @@ hth_status hth_batch_graph_create(const hth_seed* seed, const uint8_t* bytes, co
   if (st != HTH_OK) return st;
   if (count == 0) return fail(HTH_E_INVALID, "hth_batch_graph_create: count is 0");
   uint32_t grid = 0;
-  st = grid_for(out_width, seed->block, &grid);  // fills the cache outside the capture
+  st = grid_for(out_width, seed->block, &grid);  // fills the caches outside the capture
+  if (st == HTH_OK) st = tiny_grid_for(out_width, seed->block, count, &grid);
   if (st != HTH_OK) return st;
   hth_batch_graph* g = new (std::nothrow) hth_batch_graph;
   if (!g) return fail(HTH_E_OOM, "hth_batch_graph_create: host allocation");

@@ -32,7 +32,7 @@ SYMBOLS = (
     "hth_serve_reset_stats", "hth_serve_destroy", "hth_serve_pause", "hth_read_probe", "hth_entropy_words_b",
     "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words", "hth_stream_create",
     "hth_stream_update", "hth_stream_final", "hth_stream_reset", "hth_stream_save", "hth_stream_load",
-    "hth_stream_length", "hth_stream_free",
+    "hth_stream_length", "hth_stream_free", "hth_tab_words", "hth_tab_expand", "hth_hash_batch64",
 )
 
 
@@ -112,11 +112,15 @@ def lib():
         L.hth_stream_load.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.hth_stream_length.argtypes = [vp]
         L.hth_stream_free.argtypes = [vp]
+        L.hth_tab_words.argtypes = [u32]
+        L.hth_tab_expand.argtypes = [u64, u32, vp, ctypes.c_size_t]
+        L.hth_hash_batch64.argtypes = [vp, vp, vp, vp, vp, u64, vp, u32, vp]
         for name in SYMBOLS[2:]:
             getattr(L, name).restype = ctypes.c_int32
         L.hth_entropy_words_b.restype = ctypes.c_size_t
         L.hth_seed_block_words.restype = ctypes.c_uint32
         L.hth_stream_length.restype = ctypes.c_uint64
+        L.hth_tab_words.restype = ctypes.c_size_t
         for name in ("hth_expand_seed", "hth_seed_from_entropy", "hth_seed_entropy", "hth_seed_free",
                      "hth_hash_batch", "hth_hash_batch_timed", "hth_reserve", "hth_batch_check", "hth_set_tuning",
                      "hth_batch_graph_create", "hth_batch_graph_launch", "hth_batch_graph_check",
@@ -267,6 +271,50 @@ def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None, t
         _check(lib().hth_hash_batch(*args))
     else:
         _check(lib().hth_hash_batch_timed(*args, timer.start, timer.stop))
+    return out
+
+
+def tab_words(inner_width):
+    """Words of the tabulation tables of the composed 64-bit hash: (c + 1) * 256."""
+    n = int(lib().hth_tab_words(inner_width))
+    if not n:
+        raise HthError(HTH_E_INVALID, f"inner width {inner_width} is not 16/24/32/40")
+    return n
+
+
+def tab_tables(user_seed, inner_width, device="cuda"):
+    """Tabulation tables from splitmix64 started at user_seed (pick one
+    independent of the hashing seed's), as an int64 tensor on `device`."""
+    import torch
+    host = np.zeros(tab_words(inner_width), dtype=np.uint64)
+    _check(lib().hth_tab_expand(ctypes.c_uint64(user_seed & (2**64 - 1)), inner_width,
+                                ctypes.c_void_p(host.ctypes.data), host.size))
+    return torch.from_numpy(host.view(np.int64)).to(device)
+
+
+def hash_batch64(seed, tables, data, offsets, lengths, inner_width, out=None, stream=None):
+    """The composed 64-bit hash of data[offsets[i] : offsets[i] + lengths[i]]:
+    simple tabulation of the string itself when it has at most inner_width
+    bytes, else of its HalftimeHash value of that width.  tables: int64 CUDA
+    tensor from tab_tables; returns an int64 CUDA tensor of count values
+    (read the bits as unsigned)."""
+    import torch
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 CUDA tensor")
+    for t in (offsets, lengths, tables):
+        if t.dtype not in (torch.int64, torch.uint64) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("offsets, lengths and tables must be contiguous int64 CUDA tensors")
+    if tables.numel() != tab_words(inner_width):
+        raise ValueError(f"tables hold {tables.numel()} words, width {inner_width} needs {tab_words(inner_width)}")
+    count = offsets.numel()
+    if lengths.numel() != count:
+        raise ValueError("offsets and lengths differ in size")
+    if out is None:
+        out = torch.empty(count, dtype=torch.int64, device=data.device)
+    dp = data.data_ptr() if data.numel() else offsets.data_ptr()
+    _check(lib().hth_hash_batch64(seed.handle, ctypes.c_void_p(tables.data_ptr()), ctypes.c_void_p(dp),
+                                  ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(lengths.data_ptr()), count,
+                                  ctypes.c_void_p(out.data_ptr()), inner_width, _stream(stream)))
     return out
 
 

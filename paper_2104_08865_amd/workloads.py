@@ -143,6 +143,12 @@ def lognormal_lengths(seed=5, n=100_000, median=4096, sigma=2.0, cap=16 << 20):
     return np.clip(lens, 1, cap).astype(np.uint64)
 
 
+def short_key_lengths(seed=7, n=1 << 24, hi=64):
+    """Hash-table keys: lengths uniform over 0 .. hi bytes."""
+    u = uniform01(seed + 4000, n)
+    return np.minimum((u * (hi + 1)).astype(np.uint64), np.uint64(hi))
+
+
 def poisson_gaps(seed, n, rate):
     """Exponential inter-arrival gaps (seconds) for `rate` arrivals per second."""
     u = uniform01(seed + 2000, n)

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "hth.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hth_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hth_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +35,7 @@ def test_header_declares_the_entry_points():
 def test_every_declared_symbol_is_exported(lib):
     from paper_2104_08865_amd import hth
     out = subprocess.run(["nm", "-D", "--defined-only", hth.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (hth_[a-z_]+)\b", out))
+    exported = set(re.findall(r"\bT (hth_[a-z0-9_]+)\b", out))
     missing = [n for n in _declared() if n not in exported]
     assert not missing, missing
     assert set(hth.SYMBOLS) <= exported
@@ -131,3 +131,28 @@ def test_stream_argument_checks(lib):
     assert lib.hth_stream_save(None, None, ctypes.byref(n), None) == hth.HTH_E_INVALID
     assert lib.hth_stream_length(None) == 0
     assert lib.hth_stream_free(None) == hth.HTH_OK
+
+
+def test_composition_entry_points(lib, oracle_lib):
+    """hth_tab_words / hth_tab_expand on the host (the tables equal the
+    oracle's splitmix64 expansion) and hth_hash_batch64's host-side checks."""
+    import numpy as np
+    from paper_2104_08865_amd import hth
+    for w in (16, 24, 32, 40):
+        assert lib.hth_tab_words(w) == (w + 1) * 256
+        t = np.zeros((w + 1) * 256, dtype=np.uint64)
+        assert lib.hth_tab_expand(3, w, ctypes.c_void_p(t.ctypes.data), t.size) == hth.HTH_OK
+        assert (t == oracle_lib.tab_expand(3, w).ravel()).all()
+        assert lib.hth_tab_expand(3, w, ctypes.c_void_p(t.ctypes.data), t.size - 1) == hth.HTH_E_INVALID
+    assert lib.hth_tab_words(20) == 0
+    assert lib.hth_tab_expand(3, 20, None, 0) == hth.HTH_E_INVALID
+    assert lib.hth_tab_expand(3, 16, None, 17 * 256) == hth.HTH_E_INVALID
+    p, q = ctypes.c_void_p(8), ctypes.c_void_p(12)
+    assert lib.hth_hash_batch64(p, None, p, p, p, 1, p, 16, None) == hth.HTH_E_INVALID
+    assert b"tables" in lib.hth_last_error()
+    assert lib.hth_hash_batch64(p, q, p, p, p, 1, p, 16, None) == hth.HTH_E_INVALID
+    assert lib.hth_hash_batch64(p, p, p, p, p, 1, q, 16, None) == hth.HTH_E_INVALID
+    assert b"aligned" in lib.hth_last_error()
+    assert lib.hth_hash_batch64(p, p, p, p, p, 1, p, 20, None) == hth.HTH_E_INVALID
+    assert lib.hth_hash_batch64(None, p, p, p, p, 1, p, 16, None) == hth.HTH_E_INVALID
+    assert lib.hth_hash_batch64(p, None, None, None, None, 0, None, 16, None) == hth.HTH_OK
