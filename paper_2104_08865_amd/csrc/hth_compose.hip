@@ -16,21 +16,37 @@ namespace hth {
 namespace {
 
 // One workgroup of kTabThreads per compute unit shares one LDS copy of the
-// tables ((c + 1) * 2 KiB); its threads take strings with a grid stride.
+// tables ((c + 1) * 2 KiB); its threads take strings with a grid stride,
+// loading the next string's offset, length and HalftimeHash value (every row
+// of h exists; a short string's row is simply not used) while the current
+// one is tabulated.
 template <int C>
 __global__ __launch_bounds__(kTabThreads) void tab_kernel(TabArgs a) {
   constexpr int NW = C / 8;
   __shared__ uint64_t T[(C + 1) * 256];
   for (int i = threadIdx.x; i < (C + 1) * 256; i += kTabThreads) T[i] = a.tables[i];
-  __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * kTabThreads;
-  for (uint64_t s = (uint64_t)blockIdx.x * kTabThreads + threadIdx.x; s < a.count; s += stride) {
-    const uint64_t L = a.lengths[s];
+  auto fetch = [&](uint64_t i, uint64_t& L, uint64_t& off, uint64_t (&hv)[NW]) {
+    if (i < a.count) {
+      L = a.lengths[i];
+      off = a.offsets[i];
+      const uint64_t* h = reinterpret_cast<const uint64_t*>(a.h + i * C);
+#pragma unroll
+      for (int j = 0; j < NW; ++j) hv[j] = h[j];
+    }
+  };
+  uint64_t s = (uint64_t)blockIdx.x * kTabThreads + threadIdx.x;
+  uint64_t L = 0, off = 0, hv[NW];
+  fetch(s, L, off, hv);
+  __syncthreads();
+  for (; s < a.count; s += stride) {
+    uint64_t Ln = 0, offn = 0, hn[NW];
+    fetch(s + stride, Ln, offn, hn);
     uint64_t w[NW];
     uint32_t sep;
     if (L <= (uint64_t)C) {
       // the string itself, zero-padded (unrolled: constant register indices)
-      const uint8_t* p = a.bytes + a.offsets[s];
+      const uint8_t* p = a.bytes + off;
 #pragma unroll
       for (int j = 0; j < NW; ++j) w[j] = 0;
 #pragma unroll
@@ -38,15 +54,18 @@ __global__ __launch_bounds__(kTabThreads) void tab_kernel(TabArgs a) {
         if ((uint64_t)i < L) w[i / 8] |= (uint64_t)p[i] << (8 * (i % 8));
       sep = (uint32_t)L;
     } else {
-      const uint64_t* h = reinterpret_cast<const uint64_t*>(a.h + s * C);
 #pragma unroll
-      for (int j = 0; j < NW; ++j) w[j] = h[j];
+      for (int j = 0; j < NW; ++j) w[j] = hv[j];
       sep = 255;
     }
     uint64_t z = T[C * 256 + sep];
 #pragma unroll
     for (int i = 0; i < C; ++i) z ^= T[i * 256 + (uint32_t)((w[i / 8] >> (8 * (i % 8))) & 0xFF)];
     a.out[s] = z;
+    L = Ln;
+    off = offn;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) hv[j] = hn[j];
   }
 }
 

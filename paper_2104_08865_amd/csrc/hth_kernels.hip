@@ -204,7 +204,11 @@ __device__ __forceinline__ void plan_counts(uint64_t N, int j, uint32_t pass_log
   const int shift = (int)pass_log2 + 3 * j;
   tasks = (N + (1ull << shift) - 1) >> shift;
   accs = 0;
-  for (int l = j + 3; l < 22; ++l) accs += nodes_at(N, l);
+  for (int l = j + 3; l < 22; ++l) {  // nodes per level shrink to zero
+    const uint64_t n = nodes_at(N, l);
+    if (!n) break;
+    accs += n;
+  }
 }
 
 constexpr int kPlanThreads = 256;
@@ -212,10 +216,12 @@ constexpr int kPlanPer = 4;
 constexpr int kPlanBlock = kPlanThreads * kPlanPer;
 
 constexpr int kPlanWaves = kPlanThreads / 64;
+// The scan step of large plans runs in one workgroup of this many threads.
+constexpr int kScanThreads = 1024;
 
-// Sums of n values over the block, returned to every thread, with one pair
-// of barriers for all of them.
-template <int NV>
+// Sums of n values over a workgroup of NT threads, returned to every
+// thread, with one pair of barriers for all of them.
+template <int NV, int NT = kPlanThreads>
 __device__ void block_sum_n(uint64_t (&v)[NV], uint64_t (*lds)[NV]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -230,13 +236,14 @@ __device__ void block_sum_n(uint64_t (&v)[NV], uint64_t (*lds)[NV]) {
   for (int k = 0; k < NV; ++k) {
     uint64_t t = 0;
 #pragma unroll
-    for (int i = 0; i < kPlanWaves; ++i) t += lds[i][k];
+    for (int i = 0; i < NT / 64; ++i) t += lds[i][k];
     v[k] = t;
   }
 }
 
-// Exclusive prefix sum of v over the block (thread order); `total` receives
-// the block's sum.
+// Exclusive prefix sum of v over a workgroup of NT threads (thread order);
+// `total` receives the workgroup's sum.
+template <int NT = kPlanThreads>
 __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint64_t x = v;
@@ -251,7 +258,7 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
   uint64_t before = 0;
   total = 0;
 #pragma unroll
-  for (int i = 0; i < kPlanWaves; ++i) {
+  for (int i = 0; i < NT / 64; ++i) {
     if (i < w) before += lds[i];
     total += lds[i];
   }
@@ -268,10 +275,12 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t L[kPlanPer];
+#pragma unroll
   for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
   uint64_t v[kBlockSums];
   for (int j = 0; j < kPlanCandidates; ++j) {
     uint64_t t = 0, a = 0, w = 0;
+#pragma unroll
     for (int i = 0; i < kPlanPer; ++i) {
       if (base + i >= count) continue;
       uint64_t ti, ai;
@@ -285,6 +294,7 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     v[j * kPlanSums + 2] = w;
   }
   uint64_t tiny = 0;
+#pragma unroll
   for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && L[i] < exec_bytes && L[i] >= direct_lim;
   v[kBlockSums - 1] = tiny;
   block_sum_n(v, lds);
@@ -303,6 +313,7 @@ __device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_task
                             uint32_t min_j, uint32_t max_j, uint64_t target_tasks, bool write_ctl,
                             uint32_t* __restrict__ ctl, int& jsel_out, uint64_t& bucket_out) {
   uint64_t tt[kPlanCandidates], ta[kPlanCandidates], tw[kPlanCandidates];
+#pragma unroll
   for (int j = 0; j < kPlanCandidates; ++j) {
     tt[j] = tot[j * kPlanSums + 0];
     ta[j] = tot[j * kPlanSums + 1];
@@ -311,19 +322,29 @@ __device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_task
   // Task size: the coarsest level in [min_j, max_j] that still yields
   // target_tasks tasks (fewer cross-task merges, enough tasks to keep the
   // grid busy), else min_j; then coarser until the plan fits the workspace.
+  // (unrolled over the candidates: constant register indices)
   int want = (int)min_j;
-  for (int j = (int)min_j; j <= (int)max_j && j < kPlanCandidates; ++j)
-    if (tt[j] >= target_tasks) want = j;
+#pragma unroll
+  for (int j = 0; j < kPlanCandidates; ++j)
+    if (j >= (int)min_j && j <= (int)max_j && tt[j] >= target_tasks) want = j;
   int jsel = -1;
-  for (int j = want; j < kPlanCandidates && jsel < 0; ++j)
-    if (tt[j] <= cap_tasks && ta[j] <= cap_accs) jsel = j;
+  uint64_t total_work = 0;
+#pragma unroll
+  for (int j = 0; j < kPlanCandidates; ++j)
+    if (jsel < 0 && j >= want && tt[j] <= cap_tasks && ta[j] <= cap_accs) {
+      jsel = j;
+      total_work = tw[j];
+    }
   // Buckets of about equal work: at most kMaxBuckets of `bucket` bytes.
-  const uint64_t total_work = jsel >= 0 ? tw[jsel] : 0;
   uint64_t bucket = (total_work + kMaxBuckets - 1) / kMaxBuckets;
   if (bucket < kMinBucketBytes) bucket = kMinBucketBytes;
   if (write_ctl) {
     ctl[kCtlNext] = 0;
-    ctl[kCtlTotal] = jsel >= 0 ? (uint32_t)tt[jsel] : 0;
+    uint64_t ntasks = 0;
+#pragma unroll
+    for (int j = 0; j < kPlanCandidates; ++j)
+      if (j == jsel) ntasks = tt[j];
+    ctl[kCtlTotal] = (uint32_t)ntasks;
     ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
     ctl[kCtlError] = jsel >= 0 ? 0 : 1;
     ctl[kCtlTiny] = jsel >= 0 ? (uint32_t)tot[kBlockSums - 1] : 0;
@@ -359,18 +380,22 @@ __device__ void plan_fill_body(
     jsel = ctl[kCtlError] ? -1 : (int)ctl[kCtlLevel];
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
+#pragma unroll
     for (int k = 0; k <= kPlanSums; ++k) pre[k] = block_pre[(uint64_t)blk * (kPlanSums + 1) + k];
   } else {
     // Totals of every candidate over all blocks (threads stride over blocks).
     uint64_t tot[kBlockSums];
+#pragma unroll
     for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
     for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
+#pragma unroll
       for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
     block_sum_n(tot, ldsn);
     plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, blk == 0 && tid == 0, ctl, jsel, bucket);
     if (jsel < 0) return;  // uniform over the grid
     // Tasks, accumulators, work and tail-only strings of the blocks before this one.
     for (uint32_t b = tid; b < blk; b += kPlanThreads) {
+#pragma unroll
       for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)b * kBlockSums + jsel * kPlanSums + k];
       pre[kPlanSums] += block_sums[(uint64_t)b * kBlockSums + kBlockSums - 1];
     }
@@ -385,6 +410,7 @@ __device__ void plan_fill_body(
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
   uint64_t st = 0, sa = 0, sw = 0, sy = 0;
   bool tiny[kPlanPer];
+#pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
     tk[i] = ac[i] = wk[i] = 0;
     tiny[i] = false;
@@ -404,10 +430,12 @@ __device__ void plan_fill_body(
   const uint64_t ea = block_exclusive(sa, lds, blk_a);
   const uint64_t ew = block_exclusive(sw, lds, blk_w);
   uint64_t ty = tiny_base + block_exclusive(sy, lds, blk_y);
+#pragma unroll
   for (int i = 0; i < kPlanPer; ++i)
     if (tiny[i]) tiny_list[ty++] = (uint32_t)(base + i);
   uint64_t run_t = task_base + et, run_a = acc_base + ea, run_w = work_base + ew;
   uint64_t loc = et;
+#pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
     if (base + i < count) {
       task_start[base + i] = (uint32_t)run_t;
@@ -476,24 +504,26 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
 // size (control words), and every block's exclusive prefix of tasks,
 // accumulators, work and tail-only strings at that level, in one workgroup
 // (linear in the block count).  Thread t owns a contiguous run of blocks.
-__global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(
+__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint64_t* __restrict__ block_pre,
     uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
-  __shared__ uint64_t lds[kPlanWaves];
+  __shared__ uint64_t ldsn[kScanThreads / 64][kBlockSums];
+  __shared__ uint64_t lds[kScanThreads / 64];
   const int tid = threadIdx.x;
   uint64_t tot[kBlockSums];
+#pragma unroll
   for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
-  for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
+  for (uint32_t b = tid; b < nblocks; b += kScanThreads)
+#pragma unroll
     for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
-  block_sum_n(tot, ldsn);
+  block_sum_n<kBlockSums, kScanThreads>(tot, ldsn);
   int jsel;
   uint64_t bucket;
   plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, tid == 0, ctl, jsel, bucket);
   if (jsel < 0) return;  // uniform over the workgroup
   constexpr int NP = kPlanSums + 1;
-  const uint32_t per = (nblocks + kPlanThreads - 1) / kPlanThreads;
+  const uint32_t per = (nblocks + kScanThreads - 1) / kScanThreads;
   const uint32_t b0 = tid * per < nblocks ? tid * per : nblocks;
   const uint32_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
   auto value = [&](uint32_t b, int k) {
@@ -503,7 +533,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(
   for (int k = 0; k < NP; ++k) {
     uint64_t mine = 0, total = 0;
     for (uint32_t b = b0; b < b1; ++b) mine += value(b, k);
-    run[k] = block_exclusive(mine, lds, total);
+    run[k] = block_exclusive<kScanThreads>(mine, lds, total);
   }
   for (uint32_t b = b0; b < b1; ++b)
     for (int k = 0; k < NP; ++k) {
@@ -809,12 +839,11 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
 // One tail-only string: its tail words hashed with the Toeplitz keys of
 // §6.1 plus the length term, by one lane.
 template <int WIDTH, int B>
-__device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
+__device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s, uint64_t L, uint64_t off) {
   using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
   const uint64_t* __restrict__ ent = a.ent;
-  const uint64_t L = a.lengths[s];
-  const uint8_t* __restrict__ str = a.bytes + a.offsets[s];
+  const uint8_t* __restrict__ str = a.bytes + off;
   uint64_t F[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) F[t] = 0;
@@ -869,13 +898,38 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s) {
 // device atomic per chunk serialised millions of short strings).  A separate
 // kernel: inside the hashing kernel this code cost the full passes 3-10 %
 // (register allocation of the whole kernel), while a launch costs a few
-// microseconds.
+// microseconds.  The list entry of the chunk two rounds ahead and the
+// offset and length of the next round's string are loaded before the
+// current string is hashed, so a string costs one exposed memory round trip
+// instead of three.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t ntiny = uniform(a.ctl[kCtlTiny]);
-  for (uint32_t k = blockIdx.x; (uint64_t)k * kTinyChunk < ntiny; k += gridDim.x) {
-    const uint32_t idx = k * kTinyChunk + threadIdx.x;
-    if (idx < ntiny) tiny_one<WIDTH, B>(a, a.tiny_list[idx]);
+  const uint32_t G = gridDim.x;
+  auto entry = [&](uint64_t k) -> uint32_t {
+    const uint64_t idx = k * kTinyChunk + threadIdx.x;
+    return idx < ntiny ? a.tiny_list[idx] : kNone;
+  };
+  uint64_t k = blockIdx.x;
+  uint32_t s = entry(k), s1 = entry(k + G);
+  uint64_t L = 0, off = 0;
+  if (s != kNone) {
+    L = a.lengths[s];
+    off = a.offsets[s];
+  }
+  for (; k * kTinyChunk < ntiny; k += G) {
+    const uint32_t s2 = entry(k + 2 * (uint64_t)G);
+    uint64_t L1 = 0, off1 = 0;
+    if (s1 != kNone) {
+      L1 = a.lengths[s1];
+      off1 = a.offsets[s1];
+    }
+    if (s != kNone) tiny_one<WIDTH, B>(a, s, L, off);
+    s = s1;
+    s1 = s2;
+    L = L1;
+    off = off1;
   }
 }
 
@@ -1368,7 +1422,7 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (scan) {
-    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.block_sums, nblocks, p.cap_tasks,
+    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, p.block_sums, nblocks, p.cap_tasks,
                        p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.block_pre, p.ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

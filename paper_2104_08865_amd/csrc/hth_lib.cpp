@@ -73,7 +73,7 @@ std::map<std::pair<int, int>, uint32_t> g_tiny_grid;  // same keys -> resident t
 
 // Resident waves per compute unit of the tail-only kernel: it is light on
 // registers and latency-bound, so it runs deeper than the hashing kernel.
-constexpr uint32_t kTinyWavesPerCU = 16;
+constexpr uint32_t kTinyWavesPerCU = 32;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
