@@ -271,33 +271,50 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
                                 uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim,
                                 uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves][kBlockSums];
+  __shared__ uint64_t lds1[kPlanWaves][1];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
   uint64_t L[kPlanPer];
+  uint64_t N[kPlanPer];
+  bool any = false;
 #pragma unroll
-  for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
-  uint64_t v[kBlockSums];
-  for (int j = 0; j < kPlanCandidates; ++j) {
-    uint64_t t = 0, a = 0, w = 0;
-#pragma unroll
-    for (int i = 0; i < kPlanPer; ++i) {
-      if (base + i >= count) continue;
-      uint64_t ti, ai;
-      plan_counts(L[i] / exec_bytes, j, pass_log2, ti, ai);
-      t += ti;
-      a += ai;
-      w += ti ? L[i] + kTaskOverheadBytes * ti : 0;
-    }
-    v[j * kPlanSums + 0] = t;
-    v[j * kPlanSums + 1] = a;
-    v[j * kPlanSums + 2] = w;
+  for (int i = 0; i < kPlanPer; ++i) {
+    L[i] = base + i < count ? lengths[base + i] : 0;
+    N[i] = L[i] / exec_bytes;
+    any |= N[i] != 0;
   }
+  uint64_t v[kBlockSums];
+#pragma unroll
+  for (int k = 0; k < kBlockSums; ++k) v[k] = 0;
   uint64_t tiny = 0;
 #pragma unroll
-  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && L[i] < exec_bytes && L[i] >= direct_lim;
-  v[kBlockSums - 1] = tiny;
-  block_sum_n(v, lds);
+  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && N[i] == 0 && L[i] >= direct_lim;
+  // a block of tail-only strings (common in batches of short keys) has no
+  // tasks at any level: only its tail-only count is summed
+  if (!__syncthreads_or(any)) {
+    uint64_t t1[1] = {tiny};
+    block_sum_n(t1, lds1);
+    v[kBlockSums - 1] = t1[0];
+  } else {
+#pragma unroll
+    for (int j = 0; j < kPlanCandidates; ++j) {
+      uint64_t t = 0, a = 0, w = 0;
+#pragma unroll
+      for (int i = 0; i < kPlanPer; ++i) {
+        uint64_t ti, ai;
+        plan_counts(N[i], j, pass_log2, ti, ai);
+        t += ti;
+        a += ai;
+        w += ti ? L[i] + kTaskOverheadBytes * ti : 0;
+      }
+      v[j * kPlanSums + 0] = t;
+      v[j * kPlanSums + 1] = a;
+      v[j * kPlanSums + 2] = w;
+    }
+    v[kBlockSums - 1] = tiny;
+    block_sum_n(v, lds);
+  }
   if (threadIdx.x < kBlockSums) {
     uint64_t x = v[0];
     for (int k = 1; k < kBlockSums; ++k)
@@ -356,10 +373,11 @@ __device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_task
 }
 
 // Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
-// Without block_pre, the workgroup sums the other blocks' step-1 results
-// itself (cost grows with the square of the block count: small plans);
-// with it, the scan kernel has chosen the task level and bucket size (control
-// words) and written each block's prefix (block_pre[blk]).
+// Without PRE, the workgroup sums the other blocks' step-1 results itself
+// (cost grows with the square of the block count: small plans); with PRE,
+// the scan kernel has chosen the task level and bucket size (control words)
+// and written each block's prefix (block_pre[blk]).
+template <bool PRE>
 __device__ void plan_fill_body(
     uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
     uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
@@ -376,7 +394,7 @@ __device__ void plan_fill_body(
   int jsel;
   uint64_t bucket;
   uint64_t pre[kPlanSums + 1] = {0, 0, 0, 0};
-  if (block_pre) {
+  if constexpr (PRE) {
     jsel = ctl[kCtlError] ? -1 : (int)ctl[kCtlLevel];
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
@@ -425,19 +443,24 @@ __device__ void plan_fill_body(
     sw += wk[i];
     sy += tiny[i];
   }
-  uint64_t blk_t, blk_a, blk_w, blk_y;
-  const uint64_t et = block_exclusive(st, lds, blk_t);
-  const uint64_t ea = block_exclusive(sa, lds, blk_a);
-  const uint64_t ew = block_exclusive(sw, lds, blk_w);
+  const bool any = __syncthreads_or(st != 0) != 0;
+  uint64_t blk_y;
   uint64_t ty = tiny_base + block_exclusive(sy, lds, blk_y);
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i)
     if (tiny[i]) tiny_list[ty++] = (uint32_t)(base + i);
+  // a block without tasks (tail-only strings) is done: no task table
+  // entries, offsets or bucket leaders (uniform over the workgroup)
+  if (!any) return;
+  uint64_t blk_t, blk_a, blk_w;
+  const uint64_t et = block_exclusive(st, lds, blk_t);
+  const uint64_t ea = block_exclusive(sa, lds, blk_a);
+  const uint64_t ew = block_exclusive(sw, lds, blk_w);
   uint64_t run_t = task_base + et, run_a = acc_base + ea, run_w = work_base + ew;
   uint64_t loc = et;
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
-    if (base + i < count) {
+    if (tk[i]) {  // read only for strings with tasks
       task_start[base + i] = (uint32_t)run_t;
       acc_start[base + i] = (uint32_t)run_a;
     }
@@ -529,19 +552,33 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
   auto value = [&](uint32_t b, int k) {
     return block_sums[(uint64_t)b * kBlockSums + (k < kPlanSums ? jsel * kPlanSums + k : kBlockSums - 1)];
   };
-  uint64_t run[NP];
-  for (int k = 0; k < NP; ++k) {
-    uint64_t mine = 0, total = 0;
-    for (uint32_t b = b0; b < b1; ++b) mine += value(b, k);
-    run[k] = block_exclusive<kScanThreads>(mine, lds, total);
-  }
+  // (the row loops are unrolled so that several rows' loads are in flight)
+  uint64_t run[NP], mine[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) mine[k] = 0;
+#pragma unroll 4
   for (uint32_t b = b0; b < b1; ++b)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) mine[k] += value(b, k);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    uint64_t total = 0;
+    run[k] = block_exclusive<kScanThreads>(mine[k], lds, total);
+  }
+#pragma unroll 4
+  for (uint32_t b = b0; b < b1; ++b) {
+    uint64_t x[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) x[k] = value(b, k);
+#pragma unroll
     for (int k = 0; k < NP; ++k) {
       block_pre[(uint64_t)b * NP + k] = run[k];
-      run[k] += value(b, k);
+      run[k] += x[k];
     }
+  }
 }
 
+template <bool PRE>
 __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
     uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
@@ -549,7 +586,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_fill_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, nblocks, block_pre, cap_tasks, cap_accs, min_j, max_j,
+  plan_fill_body<PRE>(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, nblocks, block_pre, cap_tasks, cap_accs, min_j, max_j,
                  target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -564,7 +601,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
     uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
   plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl);
   __syncthreads();
-  plan_fill_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, 1, nullptr, cap_tasks, cap_accs, min_j, max_j, target_tasks,
+  plan_fill_body<false>(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, 1, nullptr, cap_tasks, cap_accs, min_j, max_j, target_tasks,
                  task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
@@ -1427,10 +1464,16 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(plan_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks,
-                     scan ? (const uint64_t*)p.block_pre : nullptr, p.cap_tasks, p.cap_accs, p.min_j, p.max_j,
-                     p.target_tasks, p.task_string, p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
+  if (scan)
+    hipLaunchKernelGGL(plan_fill_kernel<true>, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
+                       p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks, (const uint64_t*)p.block_pre,
+                       p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string, p.task_start,
+                       p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
+  else
+    hipLaunchKernelGGL(plan_fill_kernel<false>, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
+                       p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks, (const uint64_t*)nullptr,
+                       p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string, p.task_start,
+                       p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
   return hipGetLastError();
 }
 
