@@ -638,6 +638,10 @@ struct Ctx {
   uint64_t* gacc;
   uint32_t* gcnt;
   uint64_t* roots;  // root mode: this string's root node, [K][8] words
+  // LDS copies (per wave) of the keys of tree levels 0 and 1: tree keys
+  // [t][l * 7 + pos], final keys [t][(l * 7 + pos) * B + j]
+  const uint64_t* ltree;
+  const uint64_t* lfin;
 };
 
 // Offset of the accumulator of node `parent` at level l among one string's
@@ -776,7 +780,7 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
   const uint32_t full2 = nv / 64;  // complete level-2 nodes (fewer than NG2)
   uint64_t k0[K];                  // level-0 key of this lane's child position
 #pragma unroll
-  for (int t = 0; t < K; ++t) k0[t] = pos0 < kFan - 1 ? c.ent[Ly::tree + (t * kLevels) * (kFan - 1) + pos0] : 0;
+  for (int t = 0; t < K; ++t) k0[t] = pos0 < kFan - 1 ? c.ltree[t * 2 * (kFan - 1) + pos0] : 0;
   uint64_t s0[K], s1[K];  // terms of the current level-2 node (lanes of pos0 == 0)
 #pragma unroll
   for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
@@ -809,7 +813,7 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
         // child of the incomplete level-1 node: leftover item (0, pos0)
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 0) * (kFan - 1) + pos0) * B;
+          const uint64_t* kf = c.lfin + (t * 2 * (kFan - 1) + pos0) * B;
           F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
           F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
         }
@@ -830,7 +834,7 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
 #pragma unroll
         for (int t = 0; t < K; ++t) {
           if ((m & 7) < (uint32_t)kFan - 1) {
-            const uint64_t key = c.ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + (m & 7)];
+            const uint64_t key = c.ltree[t * 2 * (kFan - 1) + (kFan - 1) + (m & 7)];
             s0[t] = nh_acc(s0[t], t0[t], key);
             s1[t] = nh_acc(s1[t], t1[t], key);
           } else {
@@ -849,7 +853,7 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
         // complete level-1 node with an incomplete parent: leftover (1, m mod 8)
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-          const uint64_t* kf = c.ent + Ly::fin + ((t * kLevels + 1) * (kFan - 1) + (m & 7)) * B;
+          const uint64_t* kf = c.lfin + (t * 2 * (kFan - 1) + (kFan - 1) + (m & 7)) * B;
           F[t] = nh_acc(F[t], t0[t], kf[2 * r]);
           F[t] = nh_acc(F[t], t1[t], kf[2 * r + 1]);
         }
@@ -980,9 +984,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   constexpr int K = Fm::K;
   constexpr uint64_t XB = Ly::exec_bytes;
   __shared__ uint64_t lacc[kMaxLocal][K][B];
+  // Keys read at lane-varying indices by every short string and every
+  // string's last pass (tree and final keys of levels 0 and 1, the Toeplitz
+  // tail keys and the length keys), copied to LDS once per wave: they leave
+  // the chain of dependent memory round trips of a short task.
+  constexpr int NT0 = 2 * (kFan - 1);
+  constexpr int NTAIL = (int)(Ly::len + K - Ly::tail);
+  __shared__ uint64_t ltree[K * NT0];
+  __shared__ uint64_t lfin[K * NT0 * B];
+  __shared__ uint64_t ltail[NTAIL];
 
   const int lane = threadIdx.x;
   const int q = lane / Gm::LPB, r = lane % Gm::LPB;
+  for (int i = lane; i < K * NT0; i += 64)
+    ltree[i] = a.ent[Ly::tree + (i / NT0) * kLevels * (kFan - 1) + i % NT0];
+  for (int i = lane; i < K * NT0 * B; i += 64)
+    lfin[i] = a.ent[Ly::fin + (i / (NT0 * B)) * kLevels * (kFan - 1) * B + i % (NT0 * B)];
+  for (int i = lane; i < NTAIL; i += 64) ltail[i] = a.ent[Ly::tail + i];
+  __syncthreads();
   const uint32_t nb = uniform(a.ctl[kCtlBuckets]);
   const uint32_t jlev = uniform(a.ctl[kCtlLevel]);
   const uint64_t texec = (uint64_t)Gm::PASS << (3 * jlev);
@@ -1057,7 +1076,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint8_t* __restrict__ str = a.bytes + off;
 
     Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)as : 0, a.gacc, a.gcnt,
-                 ROOTS ? a.roots + (uint64_t)s * (kMaxK * kBlock) : nullptr};
+                 ROOTS ? a.roots + (uint64_t)s * (kMaxK * kBlock) : nullptr, ltree, lfin};
     uint64_t F[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = 0;
@@ -1088,12 +1107,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const uint64_t m = (uint64_t)lane + 64 * i;
         if (m < R) {
 #pragma unroll
-          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], tw[i], ent[Ly::tail + t + m]);
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], tw[i], ltail[t + m]);
         }
       }
       if (lane == 0) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ent[Ly::len + t]);
+        for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ltail[Ly::len - Ly::tail + t]);
       }
     } else {
       const uint64_t g0 = tau * texec;
@@ -1137,7 +1156,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         for (int t = 0; t < K; ++t) {
           uint64_t t0, t1;
           if (pos1 < kFan - 1) {
-            const uint64_t key = ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1];
+            const uint64_t key = ltree[t * NT0 + (kFan - 1) + pos1];
             t0 = nh_acc(0, a0[t], key);
             t1 = nh_acc(0, a1[t], key);
           } else {
@@ -1181,11 +1200,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             for (uint64_t b = 0; b < rem - 8 * m; ++b) w |= (uint64_t)pw[b] << (8 * b);
           }
 #pragma unroll
-          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ltail[t + m]);
         }
         if (lane == 0) {
 #pragma unroll
-          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ent[Ly::len + t]);
+          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ltail[Ly::len - Ly::tail + t]);
         }
       }
     }
