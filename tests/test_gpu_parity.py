@@ -239,3 +239,35 @@ def test_long_string_8gib_decompositions_agree(env):
     assert (a == b).all()
     del data
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("level", [None, 0])
+def test_large_plan_scan_path(env, level):
+    """300,000 strings (more than 256 planner blocks, so the planner's scan
+    kernel runs): tail-only strings of 0..999 bytes, every 100th string of
+    15-21 executions, every 5,000th of 600 KB (several tasks at level 0, so
+    cross-task merges).  Every string with executions and 3,000 sampled
+    others are checked against the oracle; the tail-only kernel and the
+    hashing kernel must cover every string exactly once."""
+    torch, hth = env["torch"], env["hth"]
+    width, n = 24, 300_000
+    i = np.arange(n, dtype=np.uint64)
+    lens = (i * np.uint64(2654435761)) % np.uint64(1000)
+    lens[::100] = 20_000 + (i[::100] % np.uint64(7)) * np.uint64(1000)
+    lens[::5000] = 600_000
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(61, total)
+    print(f"[parity] large plan strings={n} bytes={total} level={level}", flush=True)
+    try:
+        if level is not None:
+            hth.set_tuning(width, 0, level, level)
+        got = _gpu_hash(env, data, offs, lens, width)
+    finally:
+        hth.set_tuning(width)
+    rng = np.random.default_rng(7)
+    sel = np.unique(np.concatenate([np.nonzero(lens >= 1344)[0], rng.integers(0, n, 3000)]))
+    pieces = [data[int(offs[k]):int(offs[k] + lens[k])] for k in sel]
+    so, _ = wl.pack(lens[sel])
+    ref = env["oracle"].hash_batch(env["ent"], np.concatenate(pieces), so, lens[sel], width, nthreads=NTHREADS)
+    bad = np.nonzero((got[sel] != ref).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first string {sel[bad[0]]} (len {int(lens[sel[bad[0]]])})"
