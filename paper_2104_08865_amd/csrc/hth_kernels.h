@@ -118,12 +118,14 @@ constexpr int kTabThreads = 1024;
 // strings.  The stack holds kLevels x 7 items of kMaxK x 8 words.
 constexpr int kStackWords = 20 * 7 * kMaxK * 8;
 hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
-                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
-                              hipStream_t stream);
+// Pushes the EHC of the execution at `carry` (when not null: XB bytes in
+// device memory) as a level-0 item, then the nroots roots.
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint8_t* carry,
+                              const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
+                              uint32_t* counts, hipStream_t stream);
 // The block table of one update (device arrays), as the host plans it.
-hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint32_t has_carry, uint64_t* off,
-                               uint64_t* len, uint32_t* lev, hipStream_t stream);
+hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
+                               uint32_t* lev, hipStream_t stream);
 hipError_t launch_stream_final(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* stack,
                                const uint32_t* counts, const uint8_t* tail, uint32_t tail_len, uint64_t total_len,
                                uint8_t* out, hipStream_t stream);

@@ -1265,60 +1265,118 @@ __device__ __forceinline__ uint64_t* stack_at(uint64_t* stack, int l, int i) {
   return stack + ((uint64_t)l * (kFan - 1) + i) * (kMaxK * kBlock);
 }
 
-// Push the roots of consecutive aligned blocks (root r at level levels[r])
-// in order: an item joins its level; the 8th completes the node
-// sum_{i<7} NH(item_i, S_tree[t][l][i]) + item_7, which is pushed one level up.
+// Push, in order, the execution completed from carried bytes (when `carry`
+// is not null: its EHC is computed here, a level-0 item) and then the roots
+// of consecutive aligned blocks (root r at level levels[r]): an item joins
+// its level; the 8th completes the node sum_{i<7} NH(item_i, S_tree[t][l][i])
+// + item_7, which is pushed one level up.  The occupied levels of the stack
+// are held in LDS while the kernel runs (copied in and back with many loads
+// in flight), and each root is loaded one push ahead.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restrict__ ent,
+                                                         const uint8_t* __restrict__ carry,
                                                          const uint64_t* __restrict__ roots,
                                                          const uint32_t* __restrict__ levels, uint32_t nroots,
                                                          uint64_t* __restrict__ stack, uint32_t* __restrict__ counts) {
   using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
+  constexpr int IW = kMaxK * kBlock;  // words per stack item, [t][j]
+  constexpr int kBatch = 16;          // words per lane in flight when copying
+  __shared__ uint64_t lst[kLevels * (kFan - 1) * IW];
   const int lane = threadIdx.x;
   const bool mine = lane < K * B;
   const int t = lane / B, j = lane % B, w = t * kBlock + j;
   uint32_t cnt = lane < kLevels ? counts[lane] : 0;  // lane l holds counts[l]
-  for (uint32_t r = 0; r < nroots; ++r) {
-    int l = (int)levels[r];
-    uint64_t v = mine ? roots[(uint64_t)r * (kMaxK * kBlock) + w] : 0;
+  auto used_words = [&]() {  // the levels up to the highest occupied one
+    const uint64_t occ = __ballot(cnt != 0);
+    return occ ? (64 - __clzll((long long)occ)) * (kFan - 1) * IW : 0;
+  };
+  const int nin = used_words();
+  for (int base = 0; base < nin; base += 64 * kBatch) {
+    uint64_t buf[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int f = base + u * 64 + lane;
+      buf[u] = f < nin ? stack[f] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int f = base + u * 64 + lane;
+      if (f < nin) lst[f] = buf[u];
+    }
+  }
+  __syncthreads();
+  // one item into level l, closing full nodes upwards (each lane handles its
+  // own word w of every item, so no cross-lane LDS traffic)
+  auto push = [&](int l, uint64_t v) {
     for (;;) {
       const uint32_t c = (uint32_t)__shfl((int)cnt, l);
       if (c < kFan - 1) {
-        if (mine) stack_at(stack, l, (int)c)[w] = v;
+        if (mine) lst[(l * (kFan - 1) + (int)c) * IW + w] = v;
         if (lane == l) cnt = c + 1;
-        break;
+        return;
       }
-      // the 8th child: close the node and carry it up
       uint64_t node = v;
       if (mine) {
         for (int i = 0; i < kFan - 1; ++i)
-          node = nh_acc(node, stack_at(stack, l, i)[w], ent[Ly::tree + (t * kLevels + l) * (kFan - 1) + i]);
+          node = nh_acc(node, lst[(l * (kFan - 1) + i) * IW + w], ent[Ly::tree + (t * kLevels + l) * (kFan - 1) + i]);
       }
       if (lane == l) cnt = 0;
       v = node;
       ++l;
     }
+  };
+  if (carry) {
+    // EHC of the completed execution: lane r of the first lane group holds
+    // instances 2r and 2r + 1 (every lane group computes the same values)
+    uint64_t z0[K], z1[K];
+    ehc2<WIDTH, B>(carry + 16 * (lane % Geo<B>::LPB), uniform_keys(ent + Ly::ehc), z0, z1);
+    uint64_t v = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const uint64_t a0 = shfl64(z0[u], j >> 1), a1 = shfl64(z1[u], j >> 1);
+      if (u == t) v = (j & 1) ? a1 : a0;
+    }
+    push(0, v);
+  }
+  uint64_t nv = nroots && mine ? roots[w] : 0;
+  uint32_t nl = nroots ? levels[0] : 0;
+  for (uint32_t r = 0; r < nroots; ++r) {
+    const uint64_t v = nv;
+    const int l = (int)nl;
+    if (r + 1 < nroots) {
+      nv = mine ? roots[(uint64_t)(r + 1) * IW + w] : 0;
+      nl = levels[r + 1];
+    }
+    push(l, v);
+  }
+  // occupied levels back to the device stack, and the counts
+  const int nout = used_words();
+  for (int base = 0; base < nout; base += 64 * kBatch) {
+    uint64_t buf[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int f = base + u * 64 + lane;
+      buf[u] = f < nout ? lst[f] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int f = base + u * 64 + lane;
+      if (f < nout) stack[f] = buf[u];
+    }
   }
   if (lane < kLevels) counts[lane] = cnt;
 }
 
-// The block table of one update: optionally the execution completed from
-// carried bytes (entry 0: offset 0, one execution, level 0), then the
-// maximal aligned blocks of executions e0 .. e0 + n - 1 (block offsets
-// relative to the update's bytes, starting `pos` bytes in).  One thread: a
-// few hundred entries at most; it keeps the table off the host path.
-__global__ void stream_table_kernel(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint32_t has_carry,
+// The block table of one update: the maximal aligned blocks of executions
+// e0 .. e0 + n - 1 (block offsets relative to the update's bytes, starting
+// `pos` bytes in).  One thread: a few hundred entries at most; it keeps the
+// table off the host path.
+__global__ void stream_table_kernel(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb,
                                     uint64_t* __restrict__ off, uint64_t* __restrict__ len,
                                     uint32_t* __restrict__ lev) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t i = 0;
-  if (has_carry) {
-    off[0] = 0;
-    len[0] = xb;
-    lev[0] = 0;
-    i = 1;
-  }
   for (uint64_t x = e0, end = e0 + n; x < end;) {
     int L = 0;
     while (L + 1 < kLevels && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
@@ -1519,22 +1577,22 @@ hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
-                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
-                              hipStream_t stream) {
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint8_t* carry,
+                              const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
+                              uint32_t* counts, hipStream_t stream) {
   bool known = false;
   HTH_DISPATCH(width, block, {
-    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, roots, levels, nroots, stack,
-                       counts);
+    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, carry, roots, levels, nroots,
+                       stack, counts);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint32_t has_carry, uint64_t* off,
-                               uint64_t* len, uint32_t* lev, hipStream_t stream) {
-  hipLaunchKernelGGL(stream_table_kernel, dim3(1), dim3(64), 0, stream, e0, n, pos, xb, has_carry, off, len, lev);
+hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
+                               uint32_t* lev, hipStream_t stream) {
+  hipLaunchKernelGGL(stream_table_kernel, dim3(1), dim3(64), 0, stream, e0, n, pos, xb, off, len, lev);
   return hipGetLastError();
 }
 

@@ -146,7 +146,8 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
     st->total_len += len;
     return HTH_OK;
   }
-  // 1. the execution completed from the carried bytes (a block of level 0)
+  // 1. the execution completed from the carried bytes (its EHC is computed
+  // by the push kernel: a level-0 item)
   uint64_t pos = 0, e0 = st->executions;
   const uint32_t has_carry = st->carry_len ? 1 : 0;
   if (has_carry) {
@@ -168,16 +169,16 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
     ++nblocks;
     x += cnt;
   }
-  e = hth::launch_stream_table(e0, n, pos, xb, has_carry, st->d_off, st->d_len, st->d_lev, stream);
-  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
-  hth_status s = launch_blocks(st, st->carry, has_carry, 0, 1, stream);
-  if (s != HTH_OK) return s;
-  s = launch_blocks(st, bytes, nblocks, has_carry, waves, stream);
-  if (s != HTH_OK) return s;
-  // 3. push the roots in order
-  const uint32_t nroots = has_carry + nblocks;
+  if (nblocks) {
+    e = hth::launch_stream_table(e0, n, pos, xb, st->d_off, st->d_len, st->d_lev, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
+    hth_status s = launch_blocks(st, bytes, nblocks, 0, waves, stream);
+    if (s != HTH_OK) return s;
+  }
+  // 3. push the completed execution and the roots, in order
   const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
-  e = hth::launch_stream_push(st->width, st->block, ent, st->roots, st->d_lev, nroots, st->stack, st->counts, stream);
+  e = hth::launch_stream_push(st->width, st->block, ent, has_carry ? st->carry : nullptr, st->roots, st->d_lev,
+                              nblocks, st->stack, st->counts, stream);
   if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
   // 4. the bytes after the last full execution start the next one
   const uint64_t rem = len - pos - n * xb;
