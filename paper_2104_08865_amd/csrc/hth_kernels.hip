@@ -265,17 +265,52 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t* lds, uint64_t& total) 
   return before + x - v;
 }
 
+// Exclusive prefix sums of NV values over a workgroup of NT threads (thread
+// order), in place, with one pair of barriers; `total` receives the sums.
+template <int NV, int NT = kPlanThreads>
+__device__ void block_exclusive_n(uint64_t (&v)[NV], uint64_t (*lds)[NV], uint64_t (&total)[NV]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t x[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) x[k] = v[k];
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const uint64_t y = shfl64(x[k], lane >= d ? lane - d : lane);
+      if (lane >= d) x[k] += y;
+    }
+  __syncthreads();
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[w][k] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+      if (i < w) before += lds[i][k];
+      tot += lds[i][k];
+    }
+    v[k] = before + x[k] - v[k];
+    total[k] = tot;
+  }
+}
+
 // Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
 // accumulators and work of its kPlanBlock strings.
+// `v` receives the workgroup's sums (every thread) and `L` this thread's
+// lengths; the sums also go to block_sums[blk] unless it is null.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
                                 uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim,
-                                uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl) {
+                                uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl,
+                                uint64_t (&v)[kBlockSums], uint64_t (&L)[kPlanPer]) {
   __shared__ uint64_t lds[kPlanWaves][kBlockSums];
   __shared__ uint64_t lds1[kPlanWaves][1];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
-  uint64_t L[kPlanPer];
   uint64_t N[kPlanPer];
   bool any = false;
 #pragma unroll
@@ -284,7 +319,6 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     N[i] = L[i] / exec_bytes;
     any |= N[i] != 0;
   }
-  uint64_t v[kBlockSums];
 #pragma unroll
   for (int k = 0; k < kBlockSums; ++k) v[k] = 0;
   uint64_t tiny = 0;
@@ -315,7 +349,7 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     v[kBlockSums - 1] = tiny;
     block_sum_n(v, lds);
   }
-  if (threadIdx.x < kBlockSums) {
+  if (block_sums && threadIdx.x < kBlockSums) {
     uint64_t x = v[0];
     for (int k = 1; k < kBlockSums; ++k)
       if ((int)threadIdx.x == k) x = v[k];
@@ -372,29 +406,40 @@ __device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_task
   bucket_out = bucket;
 }
 
-// Planning step 2 for workgroup `blk` (after step 1 of every workgroup).
-// Without PRE, the workgroup sums the other blocks' step-1 results itself
-// (cost grows with the square of the block count: small plans); with PRE,
-// the scan kernel has chosen the task level and bucket size (control words)
-// and written each block's prefix (block_pre[blk]).
-template <bool PRE>
+// Planning step 2 for workgroup `blk` (after step 1 of every workgroup), in
+// one of three modes:
+//   kFillSum:    the workgroup sums the other blocks' step-1 results itself
+//                (cost grows with the square of the block count: small plans);
+//   kFillPre:    the scan kernel has chosen the task level and bucket size
+//                (control words) and written each block's prefix;
+//   kFillSingle: the only workgroup, right after its own step 1: the sums
+//                and this thread's lengths come in `tot_in` and `len_in`, and
+//                no other workgroup appends bucket leaders.
+enum { kFillSum = 0, kFillPre = 1, kFillSingle = 2 };
+template <int MODE>
 __device__ void plan_fill_body(
     uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
     uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
-    const uint64_t* __restrict__ block_pre, uint64_t cap_tasks, uint64_t cap_accs,
+    const uint64_t* __restrict__ block_pre, const uint64_t (&tot_in)[kBlockSums],
+    const uint64_t (&len_in)[kPlanPer], uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
   __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
   __shared__ uint64_t lds4[kPlanWaves][kPlanSums + 1];
+  __shared__ uint64_t lds3[kPlanWaves][kPlanSums];
   __shared__ uint32_t incl[kPlanBlock];
   __shared__ uint64_t wstart[kPlanBlock];
+  __shared__ uint64_t slen[kPlanBlock];  // the block's lengths, for the task table
   const int tid = threadIdx.x;
   int jsel;
   uint64_t bucket;
   uint64_t pre[kPlanSums + 1] = {0, 0, 0, 0};
-  if constexpr (PRE) {
+  if constexpr (MODE == kFillSingle) {
+    plan_choose(tot_in, cap_tasks, cap_accs, min_j, max_j, target_tasks, tid == 0, ctl, jsel, bucket);
+    if (jsel < 0) return;  // uniform over the workgroup
+  } else if constexpr (MODE == kFillPre) {
     jsel = ctl[kCtlError] ? -1 : (int)ctl[kCtlLevel];
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
@@ -433,7 +478,8 @@ __device__ void plan_fill_body(
     tk[i] = ac[i] = wk[i] = 0;
     tiny[i] = false;
     if (base + i < count) {
-      const uint64_t L = lengths[base + i];
+      const uint64_t L = MODE == kFillSingle ? len_in[i] : lengths[base + i];
+      slen[tid * kPlanPer + i] = L;
       plan_counts(L / exec_bytes, jsel, pass_log2, tk[i], ac[i]);
       wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
       tiny[i] = L < exec_bytes && L >= direct_lim;
@@ -452,11 +498,10 @@ __device__ void plan_fill_body(
   // a block without tasks (tail-only strings) is done: no task table
   // entries, offsets or bucket leaders (uniform over the workgroup)
   if (!any) return;
-  uint64_t blk_t, blk_a, blk_w;
-  const uint64_t et = block_exclusive(st, lds, blk_t);
-  const uint64_t ea = block_exclusive(sa, lds, blk_a);
-  const uint64_t ew = block_exclusive(sw, lds, blk_w);
-  uint64_t run_t = task_base + et, run_a = acc_base + ea, run_w = work_base + ew;
+  uint64_t ex[kPlanSums] = {st, sa, sw}, blk_tot[kPlanSums];
+  block_exclusive_n(ex, lds3, blk_tot);
+  const uint64_t et = ex[0], blk_t = blk_tot[0];
+  uint64_t run_t = task_base + et, run_a = acc_base + ex[1], run_w = work_base + ex[2];
   uint64_t loc = et;
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
@@ -492,7 +537,7 @@ __device__ void plan_fill_body(
     }
     const uint64_t task = task_base + e;
     const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
-    const uint64_t L = lengths[first + lo];
+    const uint64_t L = slen[lo];
     uint64_t ntk, nac;
     plan_counts(L / exec_bytes, jsel, pass_log2, ntk, nac);
     const uint64_t w0 = wstart[lo] + tau * unit;
@@ -501,11 +546,19 @@ __device__ void plan_fill_body(
     task_string[task] = (uint32_t)(first + lo) | (lead ? 0x80000000u : 0u);
     nlead += lead;
   }
-  // positions in bucket_lead: one atomic per workgroup
+  // positions in bucket_lead: one atomic per workgroup (none when it is the
+  // only one)
   uint64_t blk_lead;
   const uint64_t before = block_exclusive(nlead, lds, blk_lead);
   __shared__ uint32_t lead_base;
-  if (tid == 0) lead_base = blk_lead ? atomicAdd(ctl + kCtlBuckets, (uint32_t)blk_lead) : 0;
+  if (tid == 0) {
+    if constexpr (MODE == kFillSingle) {
+      lead_base = 0;
+      ctl[kCtlBuckets] = (uint32_t)blk_lead;
+    } else {
+      lead_base = blk_lead ? atomicAdd(ctl + kCtlBuckets, (uint32_t)blk_lead) : 0;
+    }
+  }
   __syncthreads();
   uint32_t at = lead_base + (uint32_t)before;
   for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
@@ -520,7 +573,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
                                                                   uint32_t pass_log2, uint32_t direct_lim,
                                                                   uint64_t* __restrict__ block_sums,
                                                                   uint32_t* __restrict__ ctl) {
-  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl);
+  uint64_t v[kBlockSums], L[kPlanPer];
+  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl, v, L);
 }
 
 // Large plans, between the two steps: totals, the task level and bucket
@@ -586,23 +640,26 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
     uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_fill_body<PRE>(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, nblocks, block_pre, cap_tasks, cap_accs, min_j, max_j,
+  const uint64_t none[kBlockSums] = {}, none_l[kPlanPer] = {};
+  plan_fill_body<PRE ? kFillPre : kFillSum>(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums,
+                                            nblocks, block_pre, none, none_l, cap_tasks, cap_accs, min_j, max_j,
                  target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
 }
 
 // Both steps in one workgroup, for batches of at most kPlanBlock strings
-// (one launch instead of two).  The barrier between the steps also makes
-// step 1's global writes visible to the whole workgroup.
+// (one launch instead of two): step 2 takes step 1's sums and lengths from
+// registers (nothing goes through block_sums).
 __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    uint32_t direct_lim, uint64_t* __restrict__ block_sums, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
+    uint32_t direct_lim, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
     uint64_t target_tasks,
     uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
     uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
-  plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl);
-  __syncthreads();
-  plan_fill_body<false>(0, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, 1, nullptr, cap_tasks, cap_accs, min_j, max_j, target_tasks,
-                 task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
+  uint64_t v[kBlockSums], L[kPlanPer];
+  plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, nullptr, ctl, v, L);
+  plan_fill_body<kFillSingle>(0, lengths, count, exec_bytes, pass_log2, direct_lim, nullptr, 1, nullptr, v, L,
+                              cap_tasks, cap_accs, min_j, max_j, target_tasks, task_string, task_start, acc_start,
+                              bucket_lead, tiny_list, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1527,7 +1584,7 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const bool scan = nblocks > kPlanScanMin;
   if (nblocks == 1) {
     hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
-                       p.pass_log2, p.direct_lim, p.block_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
+                       p.pass_log2, p.direct_lim, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
                        p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
     return hipGetLastError();
   }
