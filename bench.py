@@ -28,6 +28,7 @@ Each workload prints one JSON line of the same shape.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -51,8 +52,13 @@ def log(msg):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the kernel source with comments and blank lines removed:
+    an edit of a comment leaves the committed counters valid, any code change
+    does not."""
+    with open(KERNEL_SRC) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    code = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
+    return hashlib.sha256("\n".join(line for line in code if line.strip()).encode()).hexdigest()[:16]
 
 
 def measured_traffic(width, path=None):

@@ -3,8 +3,11 @@
 // One launch hashes a whole batch of strings.  Work is cut into tasks: a task
 // is an aligned range of T = 128 * 8^j full EHC executions of one string (the
 // last task of a string also takes its tail, its length term and any partial
-// range).  A persistent grid of single-wave workgroups pulls tasks from a
-// device counter.
+// range).  A planner (two small kernels, or one for small batches, plus a
+// scan kernel for large ones) cuts the task list into buckets of about equal
+// work; a persistent grid of single-wave workgroups pulls whole buckets from
+// a device counter.  Strings shorter than one execution have no task: a
+// separate tail-only kernel hashes them, one string per lane.
 //
 // Inside a task a wave works in passes of 128 executions.  Lane l = 4q + r
 // (q = 0..15, r = 0..3) owns instances 2r and 2r+1 (the two 64-bit words of a
@@ -23,7 +26,10 @@
 // on with the parent).  Items the stack construction of Eq. (3) leaves over
 // (one per unit of each base-8 digit of the execution count) go straight into
 // the final NH (§5.2).  All of these, the tail (§6.1) and the length term are
-// sums mod 2^64, so their order never changes the result.
+// sums mod 2^64, so their order never changes the result.  A string's last,
+// partial pass spreads its executions over all lane groups instead
+// (partial_pass), and the keys that pass and the tail read at lane-varying
+// indices are held in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
