@@ -3,10 +3,11 @@
 The kernel has two launch choices per output width (hth_set_tuning): how
 many single-wave workgroups the persistent grid keeps per compute unit, and
 the range of task sizes (128 * 8^j executions) the device planner may pick
-from.  This module times candidates on the caller's own batch with the
-kernel's HIP events, applies the fastest, and remembers it per width and
-batch shape (number of strings and total bytes, in powers of two) in a JSON
-cache file.  Every candidate computes the same values; only speed differs.
+from.  This module times candidates on the caller's own batch with HIP
+events around the whole call (planner and kernels: the task level also sets
+how many tasks the planner writes), applies the fastest, and remembers it per
+width and batch shape (number of strings and total bytes, in powers of two)
+in a JSON cache file.  Every candidate computes the same values; only speed differs.
 """
 import json
 import math
@@ -34,7 +35,9 @@ def _time(seed, data, offsets, lengths, width, out, reps):
     timers = [hth.Timer() for _ in range(reps)]
     hth.hash_batch(seed, data, offsets, lengths, width, out=out)  # plan once, warm the caches
     for t in timers:
-        hth.hash_batch(seed, data, offsets, lengths, width, out=out, timer=t)
+        t.record_start()
+        hth.hash_batch(seed, data, offsets, lengths, width, out=out)
+        t.record_stop()
     return float(np.median([t.elapsed_ms() for t in timers]))
 
 

@@ -943,10 +943,10 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
 // One tail-only string: its tail words hashed with the Toeplitz keys of
 // §6.1 plus the length term, by one lane.
 template <int WIDTH, int B>
-__device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s, uint64_t L, uint64_t off) {
+__device__ __forceinline__ void tiny_one(const MainArgs& a, const uint64_t* ltail, uint32_t s, uint64_t L,
+                                         uint64_t off) {
   using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
-  const uint64_t* __restrict__ ent = a.ent;
   const uint8_t* __restrict__ str = a.bytes + off;
   uint64_t F[K];
 #pragma unroll
@@ -960,7 +960,7 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s, uint64_t
 #pragma unroll
     for (int c = 0; c < 16; ++c)
 #pragma unroll
-      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[c], ent[Ly::tail + t + m + c]);
+      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[c], ltail[t + m + c]);
   }
   // the rest (under 128 bytes): up to 15 whole words and a zero-padded last
   // word, every load issued before the first is used
@@ -981,16 +981,16 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s, uint64_t
   for (int j = 0; j < 15; ++j)
     if ((uint32_t)j < nw) {
 #pragma unroll
-      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[j], ent[Ly::tail + t + m + j]);
+      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[j], ltail[t + m + j]);
     }
   if (nb) {
 #pragma unroll
-    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], last, ent[Ly::tail + t + m + nw]);
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], last, ltail[t + m + nw]);
   }
   uint8_t* o = a.out + (uint64_t)s * WIDTH;
 #pragma unroll
   for (int t = 0; t < K; ++t) {
-    const uint64_t v = nh_acc(F[t], L, ent[Ly::len + t]);
+    const uint64_t v = nh_acc(F[t], L, ltail[Ly::len - Ly::tail + t]);
     __builtin_memcpy(o + 8 * t, &v, 8);
   }
 }
@@ -1008,8 +1008,16 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, uint32_t s, uint64_t
 // instead of three.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
+  using Ly = Layout<WIDTH, B>;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t ntiny = uniform(a.ctl[kCtlTiny]);
+  // the Toeplitz tail keys and the length keys, read at lane-varying indices
+  // for every string, in LDS (one copy per wave)
+  constexpr int NTAIL = (int)(Ly::len + Family<WIDTH>::K - Ly::tail);
+  __shared__ uint64_t ltail[NTAIL];
+  if ((uint64_t)blockIdx.x * kTinyChunk >= ntiny) return;  // no chunk for this wave
+  for (int i = threadIdx.x; i < NTAIL; i += 64) ltail[i] = a.ent[Ly::tail + i];
+  __syncthreads();
   const uint32_t G = gridDim.x;
   auto entry = [&](uint64_t k) -> uint32_t {
     const uint64_t idx = k * kTinyChunk + threadIdx.x;
@@ -1029,7 +1037,7 @@ __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
       L1 = a.lengths[s1];
       off1 = a.offsets[s1];
     }
-    if (s != kNone) tiny_one<WIDTH, B>(a, s, L, off);
+    if (s != kNone) tiny_one<WIDTH, B>(a, ltail, s, L, off);
     s = s1;
     s1 = s2;
     L = L1;
@@ -1219,7 +1227,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         for (int t = 0; t < K; ++t) {
           uint64_t t0, t1;
           if (pos1 < kFan - 1) {
-            const uint64_t key = ltree[t * NT0 + (kFan - 1) + pos1];
+            // (HH16 runs its full passes faster with this key from the
+            // cache hierarchy than from LDS, the other widths slower:
+            // measured per width)
+            const uint64_t key = WIDTH == 16 ? ent[Ly::tree + (t * kLevels + 1) * (kFan - 1) + pos1]
+                                             : ltree[t * NT0 + (kFan - 1) + pos1];
             t0 = nh_acc(0, a0[t], key);
             t1 = nh_acc(0, a1[t], key);
           } else {
