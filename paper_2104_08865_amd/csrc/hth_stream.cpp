@@ -9,8 +9,9 @@
 // multiple of 8^L) is the same function of its bytes wherever the block
 // sits.  An update is therefore cut into maximal aligned blocks; the
 // hashing kernel in root mode computes every block's root in one launch
-// (the blocks are its strings), and a one-wave kernel pushes the roots in
-// order onto the device-resident stack.  Finishing hashes the pending items
+// (the blocks are its strings), and a one-wave kernel pushes, in order, the
+// execution completed from the carried bytes (hashing it itself) and the
+// roots onto the device-resident stack.  Finishing hashes the pending items
 // with the final keys, the pending bytes as the tail and the length.  This
 // file only plans blocks and moves bytes; all hash arithmetic is in the
 // kernels.
@@ -27,8 +28,8 @@ namespace {
 
 constexpr int kLevelsMax = 20;
 // Aligned blocks of one update: at most 7 per level on the way up to the
-// alignment of the largest block and 7 per level on the way down, plus the
-// execution completed from the carried bytes.
+// alignment of the largest block and 7 per level on the way down (with room
+// to spare).
 constexpr uint32_t kMaxRoots = 2 * 7 * kLevelsMax + 8;
 constexpr uint32_t kMaxExecBytes = 8 * 8 * 7 * 3;  // largest execution (b = 8, d = 7, w = 3)
 constexpr uint32_t kSaveMagic = 0x48544853;         // "HTHS"
@@ -65,14 +66,12 @@ namespace {
 
 hth_status stream_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
 
-// Root-mode hashing of the n blocks whose table entries start at `first`
-// (bytes relative to base); roots to st->roots + first.  waves: an upper
-// bound of their tasks.
-hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint32_t first, uint64_t waves,
-                         hipStream_t stream) {
+// Root-mode hashing of the n blocks of the table (bytes relative to base);
+// roots to st->roots.  waves: an upper bound of their tasks.
+hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint64_t waves, hipStream_t stream) {
   if (n == 0) return HTH_OK;
-  return enqueue_batch(st->seed, base, st->d_off + first, st->d_len + first, n, nullptr, st->width, st->ws, stream,
-                       nullptr, nullptr, waves, st->roots + (uint64_t)first * hth::kMaxK * 8);
+  return enqueue_batch(st->seed, base, st->d_off, st->d_len, n, nullptr, st->width, st->ws, stream, nullptr, nullptr,
+                       waves, st->roots);
 }
 
 }  // namespace
@@ -172,7 +171,7 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   if (nblocks) {
     e = hth::launch_stream_table(e0, n, pos, xb, st->d_off, st->d_len, st->d_lev, stream);
     if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
-    hth_status s = launch_blocks(st, bytes, nblocks, 0, waves, stream);
+    hth_status s = launch_blocks(st, bytes, nblocks, waves, stream);
     if (s != HTH_OK) return s;
   }
   // 3. push the completed execution and the roots, in order
