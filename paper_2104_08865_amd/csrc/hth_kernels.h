@@ -118,9 +118,12 @@ constexpr int kTabThreads = 1024;
 // strings.  The stack holds kLevels x 7 items of kMaxK x 8 words.
 constexpr int kStackWords = 20 * 7 * kMaxK * 8;
 hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
-// Pushes the EHC of the execution at `carry` (when not null: XB bytes in
-// device memory) as a level-0 item, then the nroots roots.
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint8_t* carry,
+// Pushes the EHC of the execution made of the carry_len bytes at `carry`
+// and the first XB - carry_len bytes at `head` (when carry_len > 0) as a
+// level-0 item, then the nroots roots; then copies the rest_len bytes at
+// `rest` (fewer than XB) to `carry`.
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, uint8_t* carry,
+                              uint32_t carry_len, const uint8_t* head, const uint8_t* rest, uint32_t rest_len,
                               const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
                               uint32_t* counts, hipStream_t stream);
 // The block table of one update (device arrays), as the host plans it.

@@ -1340,16 +1340,21 @@ __device__ __forceinline__ uint64_t* stack_at(uint64_t* stack, int l, int i) {
   return stack + ((uint64_t)l * (kFan - 1) + i) * (kMaxK * kBlock);
 }
 
-// Push, in order, the execution completed from carried bytes (when `carry`
-// is not null: its EHC is computed here, a level-0 item) and then the roots
-// of consecutive aligned blocks (root r at level levels[r]): an item joins
-// its level; the 8th completes the node sum_{i<7} NH(item_i, S_tree[t][l][i])
-// + item_7, which is pushed one level up.  The occupied levels of the stack
-// are held in LDS while the kernel runs (copied in and back with many loads
-// in flight), and each root is loaded one push ahead.
+// Push, in order, the execution completed from carried bytes (when
+// carry_len > 0: the carry_len bytes in `carry` followed by the first
+// bytes of the update at `head`, assembled in LDS; its EHC is computed here,
+// a level-0 item) and then the roots of consecutive aligned blocks (root r
+// at level levels[r]): an item joins its level; the 8th completes the node
+// sum_{i<7} NH(item_i, S_tree[t][l][i]) + item_7, which is pushed one level
+// up.  The occupied levels of the stack are held in LDS while the kernel runs
+// (copied in and back with many loads in flight), and each root is loaded one
+// push ahead.  Last, the update's rest_len trailing bytes at `rest` become the
+// carried bytes.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restrict__ ent,
-                                                         const uint8_t* __restrict__ carry,
+                                                         uint8_t* __restrict__ carry, uint32_t carry_len,
+                                                         const uint8_t* __restrict__ head,
+                                                         const uint8_t* __restrict__ rest, uint32_t rest_len,
                                                          const uint64_t* __restrict__ roots,
                                                          const uint32_t* __restrict__ levels, uint32_t nroots,
                                                          uint64_t* __restrict__ stack, uint32_t* __restrict__ counts) {
@@ -1357,7 +1362,10 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
   constexpr int K = Family<WIDTH>::K;
   constexpr int IW = kMaxK * kBlock;  // words per stack item, [t][j]
   constexpr int kBatch = 16;          // words per lane in flight when copying
+  constexpr uint32_t XB = Layout<WIDTH, B>::exec_bytes;
+  constexpr int kByteSteps = (int)((XB + 63) / 64);  // byte copies per lane, all in flight
   __shared__ uint64_t lst[kLevels * (kFan - 1) * IW];
+  __shared__ __attribute__((aligned(16))) uint8_t lexec[XB];
   const int lane = threadIdx.x;
   const bool mine = lane < K * B;
   const int t = lane / B, j = lane % B, w = t * kBlock + j;
@@ -1401,11 +1409,24 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
       ++l;
     }
   };
-  if (carry) {
-    // EHC of the completed execution: lane r of the first lane group holds
-    // instances 2r and 2r + 1 (every lane group computes the same values)
+  if (carry_len) {
+    // the completed execution in LDS: carried bytes, then the update's first
+    uint8_t bytes[kByteSteps];
+#pragma unroll
+    for (int u = 0; u < kByteSteps; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + lane);
+      bytes[u] = i < XB ? (i < carry_len ? carry[i] : head[i - carry_len]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kByteSteps; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + lane);
+      if (i < XB) lexec[i] = bytes[u];
+    }
+    __syncthreads();
+    // its EHC: lane r of the first lane group holds instances 2r and 2r + 1
+    // (every lane group computes the same values)
     uint64_t z0[K], z1[K];
-    ehc2<WIDTH, B>(carry + 16 * (lane % Geo<B>::LPB), uniform_keys(ent + Ly::ehc), z0, z1);
+    ehc2<WIDTH, B>(lexec + 16 * (lane % Geo<B>::LPB), uniform_keys(ent + Ly::ehc), z0, z1);
     uint64_t v = 0;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
@@ -1441,6 +1462,21 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
     }
   }
   if (lane < kLevels) counts[lane] = cnt;
+  // the trailing bytes start the next execution (the old carried bytes were
+  // read above, before the barrier)
+  {
+    uint8_t bytes[kByteSteps];
+#pragma unroll
+    for (int u = 0; u < kByteSteps; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + lane);
+      bytes[u] = i < rest_len ? rest[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kByteSteps; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + lane);
+      if (i < rest_len) carry[i] = bytes[u];
+    }
+  }
 }
 
 // The block table of one update: the maximal aligned blocks of executions
@@ -1652,13 +1688,14 @@ hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint8_t* carry,
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, uint8_t* carry,
+                              uint32_t carry_len, const uint8_t* head, const uint8_t* rest, uint32_t rest_len,
                               const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
                               uint32_t* counts, hipStream_t stream) {
   bool known = false;
   HTH_DISPATCH(width, block, {
-    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, carry, roots, levels, nroots,
-                       stack, counts);
+    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, carry, carry_len, head, rest,
+                       rest_len, roots, levels, nroots, stack, counts);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;

@@ -145,14 +145,12 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
     st->total_len += len;
     return HTH_OK;
   }
-  // 1. the execution completed from the carried bytes (its EHC is computed
-  // by the push kernel: a level-0 item)
+  // 1. the execution completed from the carried bytes and the update's
+  // first xb - carry_len bytes (assembled and hashed by the push kernel: a
+  // level-0 item)
   uint64_t pos = 0, e0 = st->executions;
-  const uint32_t has_carry = st->carry_len ? 1 : 0;
-  if (has_carry) {
+  if (st->carry_len) {
     pos = xb - st->carry_len;
-    e = hipMemcpyAsync(st->carry + st->carry_len, bytes, pos, hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
     ++e0;
   }
   // 2. the update's full executions, cut into maximal aligned blocks: the
@@ -174,17 +172,14 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
     hth_status s = launch_blocks(st, bytes, nblocks, waves, stream);
     if (s != HTH_OK) return s;
   }
-  // 3. push the completed execution and the roots, in order
-  const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
-  e = hth::launch_stream_push(st->width, st->block, ent, has_carry ? st->carry : nullptr, st->roots, st->d_lev,
-                              nblocks, st->stack, st->counts, stream);
-  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
-  // 4. the bytes after the last full execution start the next one
+  // 3. push the completed execution and the roots, in order; 4. the bytes
+  // after the last full execution start the next one (copied by the same
+  // kernel, after it has read the old carried bytes)
   const uint64_t rem = len - pos - n * xb;
-  if (rem) {
-    e = hipMemcpyAsync(st->carry, bytes + pos + n * xb, rem, hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
-  }
+  const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
+  e = hth::launch_stream_push(st->width, st->block, ent, st->carry, st->carry_len, bytes, bytes + pos + n * xb,
+                              (uint32_t)rem, st->roots, st->d_lev, nblocks, st->stack, st->counts, stream);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
   st->carry_len = (uint32_t)rem;
   st->executions = e0 + n;
   st->total_len += len;
