@@ -16,56 +16,68 @@ namespace hth {
 namespace {
 
 // One workgroup of kTabThreads per compute unit shares one LDS copy of the
-// tables ((c + 1) * 2 KiB); its threads take strings with a grid stride,
-// loading the next string's offset, length and HalftimeHash value (every row
-// of h exists; a short string's row is simply not used) while the current
-// one is tabulated.
+// tables ((c + 1) * 2 KiB); its threads take strings with a grid stride in a
+// two-deep pipeline: while string i is tabulated, the bytes of string
+// i + stride (a short one's own bytes; every row of h exists, a short
+// string's row is simply not used) and the offset, length and HalftimeHash
+// value of string i + 2 stride are in flight.
 template <int C>
 __global__ __launch_bounds__(kTabThreads) void tab_kernel(TabArgs a) {
   constexpr int NW = C / 8;
   __shared__ uint64_t T[(C + 1) * 256];
   for (int i = threadIdx.x; i < (C + 1) * 256; i += kTabThreads) T[i] = a.tables[i];
   const uint64_t stride = (uint64_t)gridDim.x * kTabThreads;
-  auto fetch = [&](uint64_t i, uint64_t& L, uint64_t& off, uint64_t (&hv)[NW]) {
+  struct Meta {
+    uint64_t L = 0, off = 0, hv[NW] = {};
+  };
+  auto fetch = [&](uint64_t i, Meta& m) {
     if (i < a.count) {
-      L = a.lengths[i];
-      off = a.offsets[i];
+      m.L = a.lengths[i];
+      m.off = a.offsets[i];
       const uint64_t* h = reinterpret_cast<const uint64_t*>(a.h + i * C);
 #pragma unroll
-      for (int j = 0; j < NW; ++j) hv[j] = h[j];
+      for (int j = 0; j < NW; ++j) m.hv[j] = h[j];
     }
   };
+  // the key's characters 0 .. C-1: a short string's zero-padded bytes (one
+  // load per byte, all issued together), else the inner value
+  auto bytes_of = [&](const Meta& m, uint8_t (&by)[C]) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) by[i] = (uint64_t)i < m.L && m.L <= (uint64_t)C ? a.bytes[m.off + i] : 0;
+  };
   uint64_t s = (uint64_t)blockIdx.x * kTabThreads + threadIdx.x;
-  uint64_t L = 0, off = 0, hv[NW];
-  fetch(s, L, off, hv);
+  Meta m0, m1;
+  fetch(s, m0);
+  fetch(s + stride, m1);
+  uint8_t b0[C];
+  bytes_of(m0, b0);
   __syncthreads();
   for (; s < a.count; s += stride) {
-    uint64_t Ln = 0, offn = 0, hn[NW];
-    fetch(s + stride, Ln, offn, hn);
+    Meta m2;
+    fetch(s + 2 * stride, m2);
+    uint8_t b1[C];
+    bytes_of(m1, b1);
     uint64_t w[NW];
     uint32_t sep;
-    if (L <= (uint64_t)C) {
-      // the string itself, zero-padded (unrolled: constant register indices)
-      const uint8_t* p = a.bytes + off;
+    if (m0.L <= (uint64_t)C) {
 #pragma unroll
       for (int j = 0; j < NW; ++j) w[j] = 0;
 #pragma unroll
-      for (int i = 0; i < C; ++i)
-        if ((uint64_t)i < L) w[i / 8] |= (uint64_t)p[i] << (8 * (i % 8));
-      sep = (uint32_t)L;
+      for (int i = 0; i < C; ++i) w[i / 8] |= (uint64_t)b0[i] << (8 * (i % 8));
+      sep = (uint32_t)m0.L;
     } else {
 #pragma unroll
-      for (int j = 0; j < NW; ++j) w[j] = hv[j];
+      for (int j = 0; j < NW; ++j) w[j] = m0.hv[j];
       sep = 255;
     }
     uint64_t z = T[C * 256 + sep];
 #pragma unroll
     for (int i = 0; i < C; ++i) z ^= T[i * 256 + (uint32_t)((w[i / 8] >> (8 * (i % 8))) & 0xFF)];
     a.out[s] = z;
-    L = Ln;
-    off = offn;
+    m0 = m1;
+    m1 = m2;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) hv[j] = hn[j];
+    for (int i = 0; i < C; ++i) b0[i] = b1[i];
   }
 }
 
