@@ -286,7 +286,7 @@ def run_throughput(args):
     if not args.no_serve:
         del data, outs
         torch.cuda.empty_cache()
-        line["latency"] = serve_legs(min(args.serve_requests, 50_000))
+        line["latency"] = serve_legs(args.serve_requests)
     return line
 
 
