@@ -147,7 +147,7 @@ def run_main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build hashes on a single MI355X and has no multi-GPU path "
+        print("bench.py measures one GPU: the library hashes on a single MI355X and has no multi-GPU path "
               "(batches would shard by string with no exchange; see the design notes). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
