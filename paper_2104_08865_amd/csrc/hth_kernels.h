@@ -49,8 +49,8 @@ struct PlanArgs {
   uint32_t exec_bytes;
   uint32_t pass_log2;     // log2 of the executions of one pass (7 for b = 8, 8 for b = 4)
   uint32_t direct_lim;    // strings shorter than this are not hashed at all (0: every string is)
-  uint64_t* block_sums;  // [nblocks][kBlockSums]
-  uint64_t* block_pre;   // [nblocks][kPlanSums + 1]: per-block prefixes (large plans)
+  uint64_t* block_sums;  // [kBlockSums][nblocks] (column-major)
+  uint64_t* block_pre;   // [kPlanSums + 1][nblocks]: per-block prefixes (large plans)
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks

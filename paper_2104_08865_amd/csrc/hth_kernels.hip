@@ -307,7 +307,7 @@ __device__ void block_exclusive_n(uint64_t (&v)[NV], uint64_t (*lds)[NV], uint64
 // Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
 // accumulators and work of its kPlanBlock strings.
 // `v` receives the workgroup's sums (every thread) and `L` this thread's
-// lengths; the sums also go to block_sums[blk] unless it is null.
+// lengths; the sums also go to column blk of block_sums unless it is null.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
                                 uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim,
                                 uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl,
@@ -355,11 +355,13 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
     v[kBlockSums - 1] = tiny;
     block_sum_n(v, lds);
   }
+  // (column-major, [kBlockSums][nblocks]: the steps that read a column over
+  // many blocks read consecutive words)
   if (block_sums && threadIdx.x < kBlockSums) {
     uint64_t x = v[0];
     for (int k = 1; k < kBlockSums; ++k)
       if ((int)threadIdx.x == k) x = v[k];
-    block_sums[(uint64_t)blk * kBlockSums + threadIdx.x] = x;
+    block_sums[(uint64_t)threadIdx.x * gridDim.x + blk] = x;
   }
 }
 
@@ -450,7 +452,7 @@ __device__ void plan_fill_body(
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
 #pragma unroll
-    for (int k = 0; k <= kPlanSums; ++k) pre[k] = block_pre[(uint64_t)blk * (kPlanSums + 1) + k];
+    for (int k = 0; k <= kPlanSums; ++k) pre[k] = block_pre[(uint64_t)k * nblocks + blk];
   } else {
     // Totals of every candidate over all blocks (threads stride over blocks).
     uint64_t tot[kBlockSums];
@@ -458,15 +460,15 @@ __device__ void plan_fill_body(
     for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
     for (uint32_t b = tid; b < nblocks; b += kPlanThreads)
 #pragma unroll
-      for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
+      for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)k * nblocks + b];
     block_sum_n(tot, ldsn);
     plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, blk == 0 && tid == 0, ctl, jsel, bucket);
     if (jsel < 0) return;  // uniform over the grid
     // Tasks, accumulators, work and tail-only strings of the blocks before this one.
     for (uint32_t b = tid; b < blk; b += kPlanThreads) {
 #pragma unroll
-      for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)b * kBlockSums + jsel * kPlanSums + k];
-      pre[kPlanSums] += block_sums[(uint64_t)b * kBlockSums + kBlockSums - 1];
+      for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)(jsel * kPlanSums + k) * nblocks + b];
+      pre[kPlanSums] += block_sums[(uint64_t)(kBlockSums - 1) * nblocks + b];
     }
     block_sum_n(pre, lds4);
   }
@@ -586,54 +588,70 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
 // Large plans, between the two steps: totals, the task level and bucket
 // size (control words), and every block's exclusive prefix of tasks,
 // accumulators, work and tail-only strings at that level, in one workgroup
-// (linear in the block count).  Thread t owns a contiguous run of blocks.
+// (linear in the block count).  Wave w owns a contiguous run of blocks, so
+// its loads read consecutive words of one column (a single workgroup is
+// bound by its cache-line requests and round trips, not by bytes); the run's
+// prefixes are wave scans, offset by the earlier waves' totals of the first
+// pass.
 __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint64_t* __restrict__ block_pre,
     uint32_t* __restrict__ ctl) {
-  __shared__ uint64_t ldsn[kScanThreads / 64][kBlockSums];
-  __shared__ uint64_t lds[kScanThreads / 64];
-  const int tid = threadIdx.x;
+  constexpr int NP = kPlanSums + 1, NW = kScanThreads / 64;
+  __shared__ uint64_t ldsn[NW][kBlockSums];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t per = (nblocks + NW - 1) / NW;
+  const uint32_t r0 = w * per < nblocks ? w * per : nblocks;
+  const uint32_t r1 = r0 + per < nblocks ? r0 + per : nblocks;
+  // totals of every column; ldsn keeps each wave's totals
   uint64_t tot[kBlockSums];
 #pragma unroll
   for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
-  for (uint32_t b = tid; b < nblocks; b += kScanThreads)
+#pragma unroll 2  // two rows of loads in flight, without spills
+  for (uint32_t b = r0 + lane; b < r1; b += 64)
 #pragma unroll
-    for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)b * kBlockSums + k];
+    for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)k * nblocks + b];
   block_sum_n<kBlockSums, kScanThreads>(tot, ldsn);
   int jsel;
   uint64_t bucket;
-  plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, tid == 0, ctl, jsel, bucket);
+  plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, threadIdx.x == 0, ctl, jsel, bucket);
   if (jsel < 0) return;  // uniform over the workgroup
-  constexpr int NP = kPlanSums + 1;
-  const uint32_t per = (nblocks + kScanThreads - 1) / kScanThreads;
-  const uint32_t b0 = tid * per < nblocks ? tid * per : nblocks;
-  const uint32_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
-  auto value = [&](uint32_t b, int k) {
-    return block_sums[(uint64_t)b * kBlockSums + (k < kPlanSums ? jsel * kPlanSums + k : kBlockSums - 1)];
-  };
-  // (the row loops are unrolled so that several rows' loads are in flight)
-  uint64_t run[NP], mine[NP];
-#pragma unroll
-  for (int k = 0; k < NP; ++k) mine[k] = 0;
-#pragma unroll 4
-  for (uint32_t b = b0; b < b1; ++b)
-#pragma unroll
-    for (int k = 0; k < NP; ++k) mine[k] += value(b, k);
+  // prefixes: rounds of 256 blocks per wave, lane l taking blocks 4l .. 4l + 3
+  // of the round (the next round's values load during this one's scan)
+  const uint64_t* col[NP];
+  uint64_t carry[NP], x[NP][4];
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    uint64_t total = 0;
-    run[k] = block_exclusive<kScanThreads>(mine[k], lds, total);
-  }
-#pragma unroll 4
-  for (uint32_t b = b0; b < b1; ++b) {
-    uint64_t x[NP];
+    const int c = k < kPlanSums ? jsel * kPlanSums + k : kBlockSums - 1;
+    col[k] = block_sums + (uint64_t)c * nblocks;
+    carry[k] = wave_sum64(lane < w ? ldsn[lane][c] : 0);  // the earlier waves' blocks
 #pragma unroll
-    for (int k = 0; k < NP; ++k) x[k] = value(b, k);
+    for (int i = 0; i < 4; ++i) x[k][i] = r0 + 4 * lane + i < r1 ? col[k][r0 + 4 * lane + i] : 0;
+  }
+  for (uint32_t b0 = r0; b0 < r1; b0 += 256) {  // uniform over the wave
+    const uint32_t b = b0 + 4 * lane, bn = b + 256;
+    uint64_t nx[NP][4];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nx[k][i] = bn + i < r1 ? col[k][bn + i] : 0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      block_pre[(uint64_t)b * NP + k] = run[k];
-      run[k] += x[k];
+      const uint64_t mine = x[k][0] + x[k][1] + x[k][2] + x[k][3];
+      uint64_t inc = mine;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = shfl64(inc, lane >= d ? lane - d : lane);
+        if (lane >= d) inc += y;
+      }
+      uint64_t run = carry[k] + inc - mine;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (b + i < r1) block_pre[(uint64_t)k * nblocks + b + i] = run;
+        run += x[k][i];
+        x[k][i] = nx[k][i];
+      }
+      carry[k] += shfl64(inc, 63);
     }
   }
 }

@@ -241,16 +241,19 @@ def test_long_string_8gib_decompositions_agree(env):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("level", [None, 0])
-def test_large_plan_scan_path(env, level):
-    """300,000 strings (more than 256 planner blocks, so the planner's scan
-    kernel runs): tail-only strings of 0..999 bytes, every 100th string of
-    15-21 executions, every 5,000th of 600 KB (several tasks at level 0, so
+@pytest.mark.parametrize("n,level", [(300_000, None), (300_000, 0), (262_145, None), (1_100_000, None)])
+def test_large_plan_scan_path(env, n, level):
+    """Plans of more than 256 planner blocks (262,144 strings), which get the
+    planner's scan kernel: 293 blocks (300,000 strings), 257 (262,145) and
+    1,075 (1.1M; the 16M-key tests of the composed hash give each wave of the
+    scan several 256-block rounds).
+    Tail-only strings of 0..999 bytes, every 100th string of 15-21
+    executions, every 5,000th of 600 KB (several tasks at level 0, so
     cross-task merges).  Every string with executions and 3,000 sampled
     others are checked against the oracle; the tail-only kernel and the
     hashing kernel must cover every string exactly once."""
     torch, hth = env["torch"], env["hth"]
-    width, n = 24, 300_000
+    width = 24
     i = np.arange(n, dtype=np.uint64)
     lens = (i * np.uint64(2654435761)) % np.uint64(1000)
     lens[::100] = 20_000 + (i[::100] % np.uint64(7)) * np.uint64(1000)
