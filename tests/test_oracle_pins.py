@@ -271,6 +271,107 @@ def test_ehc_collision_rate_w8(oracle_lib, width):
         assert coll <= _binom_upper(n_seeds, bound), (width, coll, n_seeds * bound)
 
 
+def test_ehc_swap_pair_w8(oracle_lib):
+    """§3.3 step 2: every encoded word is hashed against its own key.  For
+    HalftimeHash16 the parity item is the plain sum of the items, so swapping
+    word u between two items that agree everywhere else leaves the parity
+    item unchanged and the difference sits on exactly two systematic items.
+    With independent keys per word the pair still obeys the §4 bound
+    2^(k(p-W)); if the items shared their keys (a key picked by u alone) the
+    two items' hashes would simply trade places and the pair would collide
+    whenever NH(a, s) = NH(a + delta, s), about 2^-W of the time (2^4 times
+    the bound at W = 8)."""
+    o = oracle_lib
+    width = 16
+    d, e, k, w = o.shape(width)
+    bound = 2.0 ** (k * (P_EXP[width] - 8))
+    n_seeds = 20000
+    rng = np.random.default_rng(71)
+    S = rng.integers(0, 1 << 16, (n_seeds, e * w), dtype=np.uint64)
+    for c1, c2, u in [(2, 3, 1), (0, 5, 0), (1, 4, 2)]:
+        x = rng.integers(0, 1 << 16, d * w, dtype=np.uint64)
+        x[c2 * w:(c2 + 1) * w] = x[c1 * w:(c1 + 1) * w]
+        x[c2 * w + u] = (x[c1 * w + u] + np.uint64(0x80)) & np.uint64(0xFFFF)
+        y = x.copy()
+        y[c1 * w + u], y[c2 * w + u] = x[c2 * w + u], x[c1 * w + u]
+        # the parity item (sum of the items) is the same for both
+        assert (o.encode(width, x, W=8)[0, d * w:] == o.encode(width, y, W=8)[0, d * w:]).all()
+        zx = np.stack([o.ehc(width, x, S[i], W=8) for i in range(n_seeds)])
+        zy = np.stack([o.ehc(width, y, S[i], W=8) for i in range(n_seeds)])
+        coll = int((zx == zy).all(axis=1).sum())
+        assert coll <= _binom_upper(n_seeds, bound), (c1, c2, u, coll, n_seeds * bound)
+
+
+def _lohi(z):
+    return ((z & 0xFFFFFFFF) * (z >> 32)) & M64
+
+
+@pytest.mark.parametrize("b", [8, 4])
+@pytest.mark.parametrize("width", WIDTHS)
+def test_ehc_single_key_closed_form(oracle_lib, width, b):
+    """§3.3 step 2 with one non-zero EHC key.  All entropy zero except
+    S_ehc[idx] = s, one execution of zero bytes: every instance hashes the
+    zero word at idx against s (NH(0, s) = s_lo * s_hi) and every other word
+    to 0, so item c = idx // w has h_c = s_lo * s_hi, z_t = T[t][c] * s_lo *
+    s_hi, and the single leftover leaf of each of the b instances goes
+    through the zero final key: out_t = b * lo(z_t) * hi(z_t).  A key shared
+    by several words, or read by the wrong item, changes the multiplier or
+    the column of T."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    P, T = o.tables(width)
+    base = o.entropy_offset(width, b)
+    xb = 8 * b * d * w
+    s_lo, s_hi = 0x9E3779B1, 0x7F4A7C15
+    for idx in range(e * w):
+        ent = np.zeros(o.entropy_words(b), dtype=np.uint64)
+        ent[base + idx] = np.uint64(s_lo | (s_hi << 32))
+        out = np.frombuffer(o.hash_bytes(ent, bytes(xb), width, b=b).tobytes(), dtype="<u8")
+        for t in range(k):
+            z = int(T[t][idx // w]) * s_lo * s_hi & M64
+            assert int(out[t]) == b * _lohi(z) & M64, (idx, t)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_ehc_key_and_word_closed_form(oracle_lib, width):
+    """One non-zero input word v at (item c, sub-word u, instance 0) and one
+    non-zero EHC key s.  With the key on v's own position, v is hashed as
+    (v_lo + s_lo)(v_hi + s_hi) while every parity word that selects v
+    (binary image of P) is hashed against a zero key; with the key on a
+    position holding zero in every instance, the word's key only adds
+    s_lo * s_hi to that item in all b instances."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    P, T = o.tables(width)
+    base = o.entropy_offset(width)
+    xw = 8 * d * w
+    v_lo, v_hi = 0x01234567, 0x0089ABCD
+    s_lo, s_hi = 0x31415927, 0x02718281
+    for c, u in [(0, 0), (d - 1, 2), (1, 1)]:
+        buf = np.zeros(xw, dtype=np.uint64)
+        buf[(c * w + u) * 8] = np.uint64(v_lo | (v_hi << 32))
+        sel = [sum(_mbit(int(P[r][c]), uu, u) for uu in range(3)) for r in range(k - 1)]
+        # (a) the key on v's own word
+        ent = np.zeros(o.entropy_words(), dtype=np.uint64)
+        ent[base + c * w + u] = np.uint64(s_lo | (s_hi << 32))
+        out = np.frombuffer(o.hash_bytes(ent, buf.astype("<u8").tobytes(), width).tobytes(), dtype="<u8")
+        own = (v_lo + s_lo) * (v_hi + s_hi)
+        for t in range(k):
+            z0 = (int(T[t][c]) * own + sum(int(T[t][d + r]) * sel[r] for r in range(k - 1)) * v_lo * v_hi) & M64
+            zj = int(T[t][c]) * s_lo * s_hi & M64  # instances 1..7: zero word, key s
+            assert int(out[t]) == (_lohi(z0) + 7 * _lohi(zj)) & M64, (c, u, t)
+        # (b) the key on the next item's word u (zero in every instance)
+        c2 = (c + 1) % d
+        ent = np.zeros(o.entropy_words(), dtype=np.uint64)
+        ent[base + c2 * w + u] = np.uint64(s_lo | (s_hi << 32))
+        out = np.frombuffer(o.hash_bytes(ent, buf.astype("<u8").tobytes(), width).tobytes(), dtype="<u8")
+        for t in range(k):
+            ab = (int(T[t][c]) + sum(int(T[t][d + r]) * sel[r] for r in range(k - 1))) * v_lo * v_hi
+            z0 = (ab + int(T[t][c2]) * s_lo * s_hi) & M64
+            zj = int(T[t][c2]) * s_lo * s_hi & M64
+            assert int(out[t]) == (_lohi(z0) + 7 * _lohi(zj)) & M64, (c, u, t)
+
+
 # ---------------------------------------------------------------------------
 # Tree (§3.1 Eq. (1), §5.2 Eq. (3))
 # ---------------------------------------------------------------------------
@@ -500,6 +601,66 @@ def test_full_width_no_collisions_on_adversarial_pairs(oracle_lib, width):
         for pos in flips:
             y = base.copy(); y[pos] ^= 0x80
             assert not (o.hash_bytes(ent, y, width) == h0).all()
+
+
+@pytest.mark.parametrize("b", [8, 4])
+@pytest.mark.parametrize("width", WIDTHS)
+def test_final_single_key_closed_form(oracle_lib, width, b):
+    """§5.2 and §6.1 (b*f*h*k final-NH words): each leftover item (level l,
+    position i) of tree t and instance j has its own final key
+    S_final[t][l][i][j].  Zero bytes and zero entropy except that one key s:
+    every item is 0, so out_t = s_lo * s_hi when t is the key's tree and slot
+    (l, i) is occupied (i < digit_l of the execution count in base 8), and 0
+    otherwise.  153 executions have digits (1, 3, 2)."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    offs = o.layout(width, b)
+    base = o.entropy_offset(width, b)
+    n = 153
+    digits = _digits(n, 8)
+    assert digits == [1, 3, 2]
+    data = bytes(n * 8 * b * d * w)
+    s_lo, s_hi = 0x5851F42D, 0x4C957F2D
+    cases = [(0, 0, 0, 0), (k - 1, 0, 0, b - 1), (0, 1, 2, 1), (k - 1, 2, 1, b // 2),
+             (0, 0, 1, 0), (0, 1, 3, 2), (k - 1, 2, 2, 0), (0, 3, 0, 0)]
+    for t0, l, i, j in cases:
+        ent = np.zeros(o.entropy_words(b), dtype=np.uint64)
+        ent[base + offs[2] + ((t0 * 20 + l) * 7 + i) * b + j] = np.uint64(s_lo | (s_hi << 32))
+        out = np.frombuffer(o.hash_bytes(ent, data, width, b=b).tobytes(), dtype="<u8")
+        present = l < len(digits) and i < digits[l]
+        for t in range(k):
+            want = s_lo * s_hi if (t == t0 and present) else 0
+            assert int(out[t]) == want, (t0, l, i, j, t)
+
+
+@pytest.mark.parametrize("b", [8, 4])
+@pytest.mark.parametrize("width", WIDTHS)
+def test_instance_swap_no_collisions(oracle_lib, width, b):
+    """Instances share the EHC and tree keys (§6.1 shares the EHC entropy
+    across instances) but not the final keys, so two strings that differ only
+    by trading instances j and j' (words j and j' of every block of the full
+    executions swapped, tail untouched) give leftover items that trade
+    places between instances, and the per-instance final keys separate them:
+    no collisions at W = 32 over 60 seeds.  Were the final key shared by the
+    instances, every such pair would collide."""
+    o = oracle_lib
+    d, e, k, w = o.shape(width)
+    xb = 8 * b * d * w
+    n = 9  # leftover items at levels 0 and 1
+    x = wl.random_bytes(40 + width, n * xb + 100)
+    pairs = [(0, 1), (2, b - 1)] if b == 8 else [(0, 3), (1, 2)]
+    ys = []
+    for j1, j2 in pairs:
+        y = x.copy()
+        blocks = y[:n * xb].view("<u8").reshape(-1, b)
+        blocks[:, [j1, j2]] = blocks[:, [j2, j1]]
+        assert not (y == x).all()
+        ys.append(y)
+    for s in range(60):
+        ent = o.expand_seed(5000 + s, b=b)
+        h0 = o.hash_bytes(ent, x, width, b=b)
+        for y in ys:
+            assert not (o.hash_bytes(ent, y, width, b=b) == h0).all(), s
 
 
 @pytest.mark.parametrize("width", WIDTHS)
