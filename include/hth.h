@@ -285,7 +285,11 @@ hth_status hth_stream_save(hth_stream *st, void *host, size_t *size, hipStream_t
 
 /* Resume: load a state saved from a stream of the same width and family
    (synchronous on `stream`).  Errors: HTH_E_INVALID (not a saved state,
-   other width or family, truncated), HTH_E_HIP. */
+   other width or family, truncated, or a state that appending cannot
+   produce: a stack level whose item count is not the matching base-8 digit
+   of the execution count, or a byte count other than executions times the
+   execution size plus the carried bytes; checked before any copy),
+   HTH_E_HIP. */
 hth_status hth_stream_load(hth_stream *st, const void *host, size_t size, hipStream_t stream);
 
 /* Bytes appended so far (0 for null). */

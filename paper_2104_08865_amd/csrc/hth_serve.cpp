@@ -57,10 +57,16 @@ int widx(uint32_t w) { return (int)(w / 8) - 2; }
 
 // FIFO allocator over a ring of `cap` bytes.  Positions grow without bound;
 // an allocation never straddles the end of the ring (it moves to the next
-// start instead); space is released in allocation order.
+// start instead); space is released in allocation order.  An empty ring
+// starts the next allocation at the beginning of a lap, so a request of up
+// to `cap` bytes always fits once the ring has drained (without that, a
+// request of more than cap / 2 bytes could wait forever for a drained ring
+// whose head sits mid-lap).
 struct Ring {
   uint64_t cap = 0, head = 0, tail = 0;
   bool alloc(uint64_t n, uint64_t* pos) {
+    if (n > cap) return false;
+    if (head == tail && head % cap) head = tail = head - head % cap + cap;
     uint64_t p = head;
     const uint64_t at = p % cap;
     if (at + n > cap) p += cap - at;
@@ -68,6 +74,12 @@ struct Ring {
     head = p + n;
     *pos = p;
     return true;
+  }
+  // Space up to `end` is free again.  (A batch of empty requests ends where
+  // the ring stood when it was launched, which a later lap start may have
+  // passed: the tail never moves back.)
+  void release(uint64_t end) {
+    if (end > tail) tail = end;
   }
 };
 
@@ -290,10 +302,10 @@ bool retire_one(hth_server* s) {
     s->t_last = now;
     s->r_cv.notify_all();
   }
-  s->dev.tail = sl.dev_end;
+  s->dev.release(sl.dev_end);
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
-    s->host.tail = sl.host_end;
+    s->host.release(sl.host_end);
   }
   s->q_cv.notify_all();  // submitters waiting for host ring space
   sl.busy = false;
@@ -486,7 +498,7 @@ hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len,
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
     t = s->next_ticket;
-    const uint64_t old_head = s->host.head;
+    const uint64_t old_head = s->host.head, old_tail = s->host.tail;
     bool ok = s->host.alloc(pad(len), &pos);
     if (ok) {
       std::lock_guard<std::mutex> rl(s->r_mu);
@@ -494,6 +506,7 @@ hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len,
       if (en.state != kFree) {
         ok = false;
         s->host.head = old_head;  // undo: nothing was allocated after it
+        s->host.tail = old_tail;
       } else {
         en.ticket = t;
         en.state = kPending;

@@ -17,6 +17,7 @@
 // kernels.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <cstring>
 
 #include "hth_host.h"
@@ -241,6 +242,22 @@ hth_status hth_stream_load(hth_stream* st, const void* host, size_t size, hipStr
                 st->width, st->block);
   if (size < need || h.carry_len >= st->xb) return fail(HTH_E_INVALID, "hth_stream_load: truncated or corrupt state");
   const char* p = static_cast<const char*>(host);
+  // The state must be one that appending h.executions executions produces:
+  // level l of the stack holds digit l (base 8) of the execution count, and
+  // the byte count is the executions' bytes plus the carried ones.  Checked
+  // before anything reaches the device (the final kernel reads counts[l]
+  // items of a level that has room for 7).
+  uint32_t counts[kLevelsMax];
+  std::memcpy(counts, p + sizeof h, sizeof counts);
+  uint64_t rest = h.executions;
+  for (int l = 0; l < kLevelsMax; ++l, rest /= 8)
+    if (counts[l] != rest % 8)
+      return fail(HTH_E_INVALID, "hth_stream_load: level %d holds %u items, %llu executions leave %llu", l, counts[l],
+                  (unsigned long long)h.executions, (unsigned long long)(rest % 8));
+  if (rest != 0) return fail(HTH_E_INVALID, "hth_stream_load: execution count beyond the stack's levels");
+  if (h.executions > (UINT64_MAX - h.carry_len) / st->xb || h.total_len != h.executions * st->xb + h.carry_len)
+    return fail(HTH_E_INVALID, "hth_stream_load: %llu bytes do not match %llu executions and %u carried bytes",
+                (unsigned long long)h.total_len, (unsigned long long)h.executions, h.carry_len);
   hipError_t e = hipMemcpyAsync(st->counts, p + sizeof h, kLevelsMax * 4, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(st->stack, p + sizeof h + kLevelsMax * 4, (size_t)hth::kStackWords * 8, hipMemcpyHostToDevice,

@@ -95,6 +95,30 @@ def test_admission_defers_when_device_budget_is_full(env):
     assert (got == _oracle(env, data, offs, lens, widths)).all()
 
 
+def test_requests_as_large_as_both_rings(env):
+    """max_request_bytes equal to the device budget and the staging size:
+    after a small request leaves both rings' heads mid-lap, two requests of
+    exactly that size are still admitted once the rings drain (an empty ring
+    starts its next allocation at the beginning of a lap)."""
+    import time
+    hth = env["hth"]
+    cap = 1 << 20
+    lens = np.array([1000, cap, cap, 3000], dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    data = wl.random_bytes(9, total)
+    widths = np.array([16, 40, 24, 32], dtype=np.uint32)
+    got = np.zeros((lens.size, 40), dtype=np.uint8)
+    with hth.Server(env["seed"], max_device_bytes=cap, max_request_bytes=cap, host_stage_bytes=cap) as srv:
+        for i in range(lens.size):
+            t0 = time.monotonic()
+            ticket = None
+            while ticket is None:  # BUSY while the host ring holds the previous request
+                ticket = srv.submit(data[int(offs[i]):int(offs[i] + lens[i])], int(widths[i]))
+                assert time.monotonic() - t0 < 10, f"request {i} of {int(lens[i])} bytes never admitted"
+            got[i, :widths[i]] = np.frombuffer(srv.wait(ticket, int(widths[i])), dtype=np.uint8)
+    assert (got == _oracle(env, data, offs, lens, widths)).all()
+
+
 def test_limits_too_large_and_busy(env):
     hth = env["hth"]
     with hth.Server(env["seed"], max_request_bytes=1 << 20, max_outstanding=4) as srv:

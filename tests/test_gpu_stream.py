@@ -95,6 +95,48 @@ def test_stream_save_load_reset(env):
         s.free()
 
 
+def test_stream_load_rejects_tampered_states(env):
+    """A saved state that appending cannot produce is refused on the host
+    before anything is copied: a stack level holding more than 7 items, a
+    level count that is not the matching base-8 digit of the execution
+    count, an execution count or byte count that disagrees with the rest.
+    The untouched state still loads and resumes to the oracle's value."""
+    import struct
+    torch, hth, o = env["torch"], env["hth"], env["oracle"]
+    seed = hth.expand_seed(47)
+    ent = o.expand_seed(47)
+    data_np = wl.random_bytes(48, 400_000)
+    data = torch.from_numpy(data_np).cuda()
+    a = hth.Stream(seed, 16)
+    a.update(data[:250_001])  # 217 executions of 1152 bytes: digits (1, 3, 3), 8 bytes carried
+    state = bytearray(a.save())
+    hdr = "<4I2Q2I"
+    magic, version, width, block, execs, total, carry, _ = struct.unpack_from(hdr, state, 0)
+    assert (width, block, execs, total, carry) == (16, 8, 217, 250_001, 250_001 - 217 * 1152)
+    cnt_at = struct.calcsize(hdr)
+    assert list(struct.unpack_from("<20I", state, cnt_at))[:4] == [1, 3, 3, 0]
+    tampered = []
+    for lvl, val in ((0, 9), (1, 4), (3, 1), (19, 7)):
+        t = bytearray(state)
+        struct.pack_into("<I", t, cnt_at + 4 * lvl, val)
+        tampered.append(t)
+    for field, val in ((4, execs + 1), (5, total + 1), (5, total - carry)):
+        t = bytearray(state)
+        vals = list(struct.unpack_from(hdr, t, 0))
+        vals[field] = val
+        struct.pack_into(hdr, t, 0, *vals)
+        tampered.append(t)
+    b = hth.Stream(seed, 16)
+    for t in tampered:
+        with pytest.raises(hth.HthError):
+            b.load(bytes(t))
+    b.load(bytes(state))
+    b.update(data[250_001:])
+    assert (b.final().cpu().numpy() == o.hash_bytes(ent, data_np, 16)).all()
+    for s in (a, b):
+        s.free()
+
+
 def test_stream_long_string_pieces(env):
     """A 1 GiB string appended in 37 uneven pieces (blocks up to level 6)."""
     torch, hth, o = env["torch"], env["hth"], env["oracle"]
