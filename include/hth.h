@@ -217,12 +217,34 @@ hth_status hth_batch_graph_check(hth_batch_graph *graph, hipStream_t stream);
    Null is accepted. */
 hth_status hth_batch_graph_free(hth_batch_graph *graph);
 
+/* hth_hash_batch without allocation, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, values and errors as
+   hth_hash_batch; the call itself allocates nothing: the planning arrays and
+   cross-task sums live in one static device array per GPU
+   (HTH_NOALLOC_SCRATCH_BYTES, held from the first call on a device until the
+   process ends; that first call also enqueues a kernel that clears it).
+   Limits: count <= HTH_NOALLOC_MAX_COUNT (HTH_E_TOO_LARGE otherwise).  A
+   batch whose plan does not fit the array (more than about 10^14 bytes of
+   strings, reachable only with overlapping strings) produces no output, and
+   hth_batch_check on the same stream reports HTH_E_TOO_LARGE.
+   All calls on one GPU share its array: calls that overlap on one GPU (on
+   different streams, or different host threads without ordering) race and
+   give wrong values.  Order them on one stream. */
+#define HTH_NOALLOC_MAX_COUNT 65536
+#define HTH_NOALLOC_SCRATCH_BYTES 7122944
+hth_status hth_hash_batch_noalloc(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
+                                  const uint64_t *lengths, uint64_t count, uint8_t *out, uint32_t out_width,
+                                  hipStream_t stream);
+
 /* Pre-size the workspace of `stream` for batches of up to max_count strings.
    Synchronous with respect to the host.  Errors: HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_reserve(uint64_t max_count, hipStream_t stream);
 
 /* Synchronise `stream` and report whether the last batch on it was planned:
-   HTH_OK, or HTH_E_TOO_LARGE if the device rejected its size. */
+   HTH_OK, or HTH_E_TOO_LARGE if the device rejected its size (the batches of
+   hth_hash_batch on this stream, and of hth_hash_batch_noalloc when its
+   last call on the current device was on this stream). */
 hth_status hth_batch_check(hipStream_t stream);
 
 /* Diagnostic: a plain streaming read of `bytes` (rounded down to 16-byte

@@ -77,5 +77,9 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
 // task size) in the family with `block` words per block, for max_waves.
 uint64_t task_bound(uint64_t len, uint32_t out_width, uint32_t block);
 
+// Control words of the static workspace of hth_hash_batch_noalloc on device
+// `dev` when its last call there was on `stream`, else null.
+uint32_t* noalloc_ctl_for(int dev, hipStream_t stream);
+
 }  // namespace host
 }  // namespace hth

@@ -543,10 +543,13 @@ hth_status hth_batch_check(hipStream_t stream) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_ws.find({dev, stream});
-    if (it == g_ws.end()) return HTH_OK;
-    ctl = it->second.ctl;
+    if (it != g_ws.end()) ctl = it->second.ctl;
   }
-  return check_ctl(ctl, stream);
+  uint32_t* na = noalloc_ctl_for(dev, stream);
+  hth_status st = HTH_OK;
+  if (ctl) st = check_ctl(ctl, stream);
+  if (st == HTH_OK && na) st = check_ctl(na, stream);
+  return st;
 }
 
 }  // extern "C"

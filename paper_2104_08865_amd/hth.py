@@ -33,6 +33,7 @@ SYMBOLS = (
     "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words", "hth_stream_create",
     "hth_stream_update", "hth_stream_final", "hth_stream_reset", "hth_stream_save", "hth_stream_load",
     "hth_stream_length", "hth_stream_free", "hth_tab_words", "hth_tab_expand", "hth_hash_batch64",
+    "hth_hash_batch_noalloc",
 )
 
 
@@ -82,6 +83,7 @@ def lib():
         L.hth_seed_free.argtypes = [vp]
         L.hth_hash_batch.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp]
         L.hth_hash_batch_timed.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp, vp, vp]
+        L.hth_hash_batch_noalloc.argtypes = [vp, vp, vp, vp, u64, vp, u32, vp]
         L.hth_reserve.argtypes = [u64, vp]
         L.hth_batch_check.argtypes = [vp]
         L.hth_set_tuning.argtypes = [u32, u32, u32, u32]
@@ -246,6 +248,28 @@ class Timer:
             Timer._hip.hipEventDestroy(self.stop)
         except Exception:
             pass
+
+
+def hash_batch_noalloc(seed, data, offsets, lengths, out_width, out, stream=None):
+    """hash_batch through hth_hash_batch_noalloc: the library allocates
+    nothing (its scratch is a static device array of the GPU); `out` must be
+    a preallocated (count, out_width) uint8 CUDA tensor."""
+    import torch
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 CUDA tensor")
+    for t in (offsets, lengths):
+        if t.dtype not in (torch.int64, torch.uint64) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("offsets and lengths must be contiguous int64 CUDA tensors")
+    count = offsets.numel()
+    if lengths.numel() != count:
+        raise ValueError("offsets and lengths differ in size")
+    if out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < count * out_width:
+        raise TypeError("out must be a contiguous uint8 CUDA tensor of count * out_width bytes")
+    dp = data.data_ptr() if data.numel() else offsets.data_ptr()
+    _check(lib().hth_hash_batch_noalloc(seed.handle, ctypes.c_void_p(dp), ctypes.c_void_p(offsets.data_ptr()),
+                                        ctypes.c_void_p(lengths.data_ptr()), count, ctypes.c_void_p(out.data_ptr()),
+                                        out_width, _stream(stream)))
+    return out
 
 
 def hash_batch(seed, data, offsets, lengths, out_width, out=None, stream=None, timer=None):
