@@ -133,66 +133,105 @@ __device__ __forceinline__ uint64_t nodes_at(uint64_t N, int l) { return l >= 22
 // block i of the execution starts 8*B*i bytes in).
 // ---------------------------------------------------------------------------
 
-template <int WIDTH, int B>
-__device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_ehc,
-                                     uint64_t z0[], uint64_t z1[]) {
+// EHC state of one execution for the two instances of a lane: the parity
+// words (sums over the systematic words) and the k combined outputs.  The
+// systematic items can be fed in several calls, in order.
+template <int WIDTH>
+struct Ehc {
+  static constexpr int D = Family<WIDTH>::D, K = Family<WIDTH>::K, R = K - 1, RR = R > 0 ? R : 1;
+  uint64_t par0[RR][kSym], par1[RR][kSym];
+  uint64_t z0[K], z1[K];
+};
+
+template <int WIDTH>
+__device__ __forceinline__ void ehc_begin(Ehc<WIDTH>& s) {
+#pragma unroll
+  for (int r = 0; r < Ehc<WIDTH>::R; ++r)
+#pragma unroll
+    for (int u = 0; u < kSym; ++u) s.par0[r][u] = s.par1[r][u] = 0;
+#pragma unroll
+  for (int t = 0; t < Ehc<WIDTH>::K; ++t) s.z0[t] = s.z1[t] = 0;
+}
+
+// Systematic blocks K0 .. K1-1 (block k = word k % kSym of item k / kSym, in
+// x[k - K0]): hash each word, add it into the parity words whose binary image
+// selects it, and add T times the item's NH sum into the outputs.  An item
+// may be split over two calls: T is linear, so its two partial sums are
+// combined separately.
+template <int WIDTH, int K0, int K1>
+__device__ __forceinline__ void ehc_blocks(Ehc<WIDTH>& s, const uint4* x, key_ptr S_ehc) {
   using Fm = Family<WIDTH>;
-  constexpr int D = Fm::D, K = Fm::K, R = K - 1;
-  uint4 x[D * kSym];
+  constexpr int K = Fm::K, R = K - 1;
+  uint64_t h0 = 0, h1 = 0;
 #pragma unroll
-  for (int i = 0; i < D * kSym; ++i) x[i] = load16(eb + 8 * B * i);
-
-  uint64_t par0[R > 0 ? R : 1][kSym], par1[R > 0 ? R : 1][kSym];
+  for (int k = K0; k < K1; ++k) {
+    const int c = k / kSym, v = k % kSym;
+    const uint4 w = x[k - K0];
+    const uint64_t key = S_ehc[k];
+    h0 = nh_acc(h0, w.x, w.y, key);
+    h1 = nh_acc(h1, w.z, w.w, key);
+    const uint64_t w0 = (uint64_t)w.y << 32 | w.x, w1 = (uint64_t)w.w << 32 | w.z;
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int u = 0; u < kSym; ++u) par0[r][u] = par1[r][u] = 0;
+      for (int u = 0; u < kSym; ++u)
+        if (image_bit(Fm::P[r][c], u, v)) {
+          s.par0[r][u] += w0;
+          s.par1[r][u] += w1;
+        }
+    if (v == kSym - 1 || k == K1 - 1) {
 #pragma unroll
-  for (int t = 0; t < K; ++t) z0[t] = z1[t] = 0;
-
-  // systematic items: hash each word, and add it into the parity words whose
-  // binary image selects it
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    uint64_t h0 = 0, h1 = 0;
-#pragma unroll
-    for (int v = 0; v < kSym; ++v) {
-      const uint4 w = x[c * kSym + v];
-      const uint64_t key = S_ehc[c * kSym + v];
-      h0 = nh_acc(h0, w.x, w.y, key);
-      h1 = nh_acc(h1, w.z, w.w, key);
-      const uint64_t w0 = (uint64_t)w.y << 32 | w.x, w1 = (uint64_t)w.w << 32 | w.z;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int u = 0; u < kSym; ++u)
-          if (image_bit(Fm::P[r][c], u, v)) {
-            par0[r][u] += w0;
-            par1[r][u] += w1;
-          }
-    }
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      z0[t] += mulc(Fm::T[t][c], h0);
-      z1[t] += mulc(Fm::T[t][c], h1);
+      for (int t = 0; t < K; ++t) {
+        s.z0[t] += mulc(Fm::T[t][c], h0);
+        s.z1[t] += mulc(Fm::T[t][c], h1);
+      }
+      h0 = h1 = 0;
     }
   }
-  // parity items
+}
+
+// The parity items, after every systematic item.
+template <int WIDTH>
+__device__ __forceinline__ void ehc_end(Ehc<WIDTH>& s, key_ptr S_ehc) {
+  using Fm = Family<WIDTH>;
+  constexpr int D = Fm::D, K = Fm::K, R = K - 1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     uint64_t h0 = 0, h1 = 0;
 #pragma unroll
     for (int u = 0; u < kSym; ++u) {
       const uint64_t key = S_ehc[(D + r) * kSym + u];
-      h0 = nh_acc(h0, par0[r][u], key);
-      h1 = nh_acc(h1, par1[r][u], key);
+      h0 = nh_acc(h0, s.par0[r][u], key);
+      h1 = nh_acc(h1, s.par1[r][u], key);
     }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      z0[t] += mulc(Fm::T[t][D + r], h0);
-      z1[t] += mulc(Fm::T[t][D + r], h1);
+      s.z0[t] += mulc(Fm::T[t][D + r], h0);
+      s.z1[t] += mulc(Fm::T[t][D + r], h1);
     }
   }
+}
+
+template <int WIDTH, int B>
+__device__ __forceinline__ void ehc2_x(const uint4 (&x)[Family<WIDTH>::D * kSym], key_ptr S_ehc,
+                                       uint64_t z0[], uint64_t z1[]) {
+  Ehc<WIDTH> s;
+  ehc_begin(s);
+  ehc_blocks<WIDTH, 0, Family<WIDTH>::D * kSym>(s, x, S_ehc);
+  ehc_end(s, S_ehc);
+#pragma unroll
+  for (int t = 0; t < Family<WIDTH>::K; ++t) {
+    z0[t] = s.z0[t];
+    z1[t] = s.z1[t];
+  }
+}
+
+template <int WIDTH, int B>
+__device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_ehc, uint64_t z0[], uint64_t z1[]) {
+  uint4 x[Family<WIDTH>::D * kSym];
+#pragma unroll
+  for (int i = 0; i < Family<WIDTH>::D * kSym; ++i) x[i] = load16(eb + 8 * B * i);
+  ehc2_x<WIDTH, B>(x, S_ehc, z0, z1);
 }
 
 // ---------------------------------------------------------------------------
@@ -709,6 +748,218 @@ struct Geo {
   static_assert(PASS == 1 << LOG_PASS, "pass size");
 };
 
+// Staging of executions in LDS.  A wave hashes a region of G executions at a
+// time (one per lane group: G * XB bytes), staged in LDS in two parts: part A
+// holds the first blocks of every execution, part B the rest.  A part is
+// copied from HBM with 16-byte direct-to-LDS loads, non-temporal (the bytes
+// are read once); then every lane reads its instance pair of its execution's
+// blocks of the part back into registers, and the next part's copy is issued
+// before those blocks are hashed: part B of the same region while part A is
+// hashed, part A of the next region while part B is.  A wave's loads are thus
+// in flight while it computes, without holding registers, and its buffer
+// holds one part, so that enough waves fit in a compute unit's LDS.  Each load
+// instruction fills 1 KiB of the image and its lanes read runs of contiguous
+// bytes (the part of one execution): the direct pattern, 16 half-lines of 16
+// executions per load instruction, reaches a lower HBM rate.
+//
+// Part A of an execution ends at a 128-byte line boundary of its address when
+// one lies near the middle (the execution starts at a multiple of the block
+// size): blocks 0 .. cA-1 with cA = C0 + shift, shift < LB (LB blocks per
+// line).  A line split between the parts would be fetched from HBM twice
+// (non-temporal lines do not stay in the L2 until the second part's copy).
+// The registers stay static: a lane reads blocks 0 .. C0+LB-2 of part A's
+// slot and blocks C0 .. XB/8B-1 of part B's slot (part B's slot starts at block
+// C0; blocks below cA are not copied there) and takes each of the blocks
+// C0 .. C0+LB-2 from whichever part copied it.  The EHC is fed block by block
+// (ehc_blocks), so the split may fall inside an item.  In the image,
+// execution q of the region takes a slot of an odd number of blocks (padded),
+// so that the lane groups reading one block of consecutive executions in one
+// LDS access fall into different banks.
+//
+// In a full pass, lane group q hashes executions p + 8q + e in regions e = 0 ..
+// 7, so execution g + 1 follows execution g in the same lane's next region.
+// When g ends inside a line, part B also copies the blocks of g + 1 that
+// complete the line (cout of them), the lane keeps them in registers and the
+// next region's part A skips them (cin), so that line is fetched once too.
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;  // the buffer, as an LDS pointer
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(3))) u32x4 lds_u4;
+constexpr int kLoadNT = 2;  // cache policy of the copies: non-temporal
+
+template <int WIDTH, int B>
+struct Parts {
+  static constexpr int BB = 8 * B;                       // bytes per block
+  static constexpr int LB = 128 / BB;                    // blocks per 128-byte line
+  static constexpr int NBLK = Family<WIDTH>::D * kSym;   // blocks per execution
+  static constexpr int C0 = (NBLK - LB + 2) / 2;         // part A has C0 .. C0+LB-1 blocks
+  static constexpr int LX = LB - 1;                      // blocks that may move between parts
+  static constexpr int NA = C0 + LX;                     // blocks read from part A's slot
+  static constexpr int NB = NBLK - C0 + LX;              // blocks read from part B's slot (with
+                                                         // the successor's first blocks)
+  static constexpr int slot(int nb) { return nb % 2 ? nb : nb + 1; }
+  static constexpr int SA = slot(NA), SB = slot(NB);     // blocks per execution slot
+  static constexpr int BYTES = 1024 * (SA > SB ? SA : SB);  // G * slot * BB: the buffer
+  static_assert(Geo<B>::G * BB == 1024, "a region's block row is one 1 KiB load");
+  static_assert(NA <= NBLK && NB - LX >= LB, "parts");
+};
+
+// Blocks from address `at` up to the next line boundary (0 when `at` is not
+// at a block boundary: then every block straddles two lines anyway).
+template <int B>
+__device__ __forceinline__ uint32_t blocks_to_line(const uint8_t* at) {
+  constexpr uint32_t BB = 8 * B;
+  const uint32_t a = (uint32_t)reinterpret_cast<uintptr_t>(at) & 127u;
+  return a % BB ? 0 : ((128u - a) % 128u) / BB;
+}
+
+// Blocks of part A of the execution at address `at`: C0 plus the blocks up to
+// the next line boundary, when the execution starts at a block boundary.
+template <int WIDTH, int B>
+__device__ __forceinline__ uint32_t part_a_blocks(const uint8_t* at) {
+  using P = Parts<WIDTH, B>;
+  const uint32_t a = (uint32_t)reinterpret_cast<uintptr_t>(at) & 127u;
+  if (a % P::BB) return P::C0;
+  return P::C0 + ((128u - (a + P::BB * P::C0) % 128u) % 128u) / P::BB;
+}
+
+// Waits for this wave's outstanding vector memory operations (the copies into
+// LDS among them: vmcnt(0)), or for its LDS reads and scalar loads
+// (lgkmcnt(0)); the other counters are left at their maximum (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).  The compiler
+// schedules no memory operation across either wait, and values already in
+// registers (the keys) stay there.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+__device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Copy one part of the first nq executions of a region (execution q at base +
+// q * qs in HBM) into slots of S blocks.  Part A: blocks lo .. cA-1 (lo = cin
+// blocks already in registers) to slot positions lo ..; part B: blocks cA ..
+// NBLK-1+cout (the last cout of them the successor's, contiguous in HBM) to
+// slot positions cA - C0 ..  Padding, blocks of the other part and executions
+// past nq are not copied.  UNI: a full pass's region, whose G executions lie
+// a multiple of 128 bytes apart (same line alignment, one cA for all).
+template <int WIDTH, int B, bool PART_B, bool UNI>
+__device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uint32_t qs, uint32_t nq,
+                                           uint32_t cnt, lds_u8* stage) {
+  using P = Parts<WIDTH, B>;
+  constexpr uint32_t S = PART_B ? P::SB : P::SA;
+  constexpr uint32_t SLOT = S * P::BB;
+  constexpr uint32_t FIRST = PART_B ? P::C0 : 0;  // block at slot position 0
+  // copied bytes of a slot: [wlo, whi) (uniform when UNI)
+  const uint32_t ca_u = UNI ? part_a_blocks<WIDTH, B>(base) : 0;
+  // (opaque to the compiler, so that the per-lane offsets are recomputed at
+  // every copy instead of being held in registers)
+  uint32_t lane = threadIdx.x;
+  asm volatile("" : "+v"(lane));
+#pragma unroll
+  for (int i = 0; i < (int)S; ++i) {
+    const uint32_t o = 1024u * i + 16u * lane;
+    const uint32_t q = o / SLOT, w = o - q * SLOT;
+    const uint32_t ca = UNI ? ca_u : part_a_blocks<WIDTH, B>(base + q * qs);
+    const uint32_t wlo = (PART_B ? ca - P::C0 : cnt) * P::BB;
+    const uint32_t whi = PART_B ? (P::NBLK - P::C0 + cnt) * P::BB : ca * P::BB;
+    if (w >= wlo && w < whi && (UNI || q < nq))
+      __builtin_amdgcn_global_load_lds((const void*)(base + (q * qs + FIRST * P::BB + w)),
+                                       (lds_void_ptr)(stage + 1024 * i), 16, 0, kLoadNT);
+  }
+}
+
+// This lane's instance pair of N blocks of its execution's slot (S blocks).
+template <int B, int N, int S>
+__device__ __forceinline__ void read_slot(const lds_u8* stage, uint4 (&x)[N]) {
+  const int q = threadIdx.x / Geo<B>::LPB, r = threadIdx.x % Geo<B>::LPB;
+  const lds_u8* at = stage + q * (S * 8 * B) + 16 * r;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const u32x4 v = *(lds_u4*)(at + 8 * B * k);
+    x[k] = make_uint4(v.x, v.y, v.z, v.w);
+  }
+}
+
+// Part A of the region whose execution q starts at base + q * qs (nq
+// executions), without its first cin blocks.
+template <int WIDTH, int B>
+__device__ __forceinline__ void stage_first(const uint8_t* base, uint32_t qs, uint32_t nq, uint32_t cin,
+                                            lds_u8* stage) {
+  if (qs == 8u * Layout<WIDTH, B>::exec_bytes)
+    stage_part<WIDTH, B, false, true>(base, qs, nq, cin, stage);
+  else
+    stage_part<WIDTH, B, false, false>(base, qs, nq, cin, stage);
+}
+
+// Blocks of a full pass's region e that complete the last line of each of its
+// executions (copied with the region, kept for region e + 1).
+template <int WIDTH, int B>
+__device__ __forceinline__ uint32_t carry_blocks(const uint8_t* str, uint64_t p, int e) {
+  constexpr uint64_t XB = Layout<WIDTH, B>::exec_bytes;
+  // (b = 4: up to three blocks of 32 bytes would stay in registers, more
+  // than the kernel's register budget leaves; its lines are fetched twice)
+  if constexpr (B == 4) return 0;
+  return e < 7 ? blocks_to_line<B>(str + (p + e + 1) * XB) : 0;  // (uniform over the region)
+}
+
+// EHC of this lane's execution of a region whose part A is being copied (as
+// stage_first, skipping cin blocks that are in xc); part B also copies the
+// first cout blocks of every execution's successor, which go to xc for the
+// next region.  `next` (nnq > 0) is the next region, whose part A (skipping
+// ncin blocks) is copied while part B of this one is hashed.  Lanes whose
+// execution is past nq hash stale bytes (their results are not used).  Called
+// by the whole wave; cin, cout, ncin uniform, at most LB - 1.
+template <int WIDTH, int B>
+__device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, uint32_t qs, uint32_t nq,
+                                           uint32_t cin, uint32_t cout, const uint8_t* next, uint32_t nnq,
+                                           uint32_t ncin, uint4 (&xc)[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1],
+                                           key_ptr S_ehc, uint64_t z0[], uint64_t z1[]) {
+  using P = Parts<WIDTH, B>;
+  constexpr int LX = P::LX;  // blocks C0 .. C0+LX-1 may come from either part
+  const bool uni = qs == 8u * Layout<WIDTH, B>::exec_bytes;  // a full pass's region
+  Ehc<WIDTH> s;
+  ehc_begin(s);
+  const uint32_t ca = part_a_blocks<WIDTH, B>(base + (threadIdx.x / Geo<B>::LPB) * qs);
+  uint4 xe[LX > 0 ? LX : 1];  // part A's copies of blocks C0 .. C0+LX-1
+  {
+    uint4 x[P::NA];
+    wait_vm();
+    read_slot<B, P::NA, P::SA>(stage, x);
+    wait_lgkm();
+    if (uni)
+      stage_part<WIDTH, B, true, true>(base, qs, nq, cout, stage);
+    else
+      stage_part<WIDTH, B, true, false>(base, qs, nq, cout, stage);
+#pragma unroll
+    for (int k = 0; k < LX; ++k) xe[k] = x[P::C0 + k];
+#pragma unroll
+    for (int k = 0; k < LX; ++k)
+      if ((uint32_t)k < cin) x[k] = xc[k];
+    ehc_blocks<WIDTH, 0, P::C0>(s, x, S_ehc);
+  }
+  {
+    uint4 x[P::NB];
+    wait_vm();
+    read_slot<B, P::NB, P::SB>(stage, x);
+    wait_lgkm();
+    if (nnq) {
+      if (uni)
+        stage_part<WIDTH, B, false, true>(next, qs, nnq, ncin, stage);
+      else
+        stage_part<WIDTH, B, false, false>(next, qs, nnq, ncin, stage);
+    }
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+      if ((uint32_t)(P::C0 + k) < ca) x[k] = xe[k];
+      xc[k] = x[P::NB - LX + k];
+    }
+    ehc_blocks<WIDTH, P::C0, P::NBLK>(s, x, S_ehc);
+  }
+  ehc_end(s, S_ehc);
+#pragma unroll
+  for (int t = 0; t < Family<WIDTH>::K; ++t) {
+    z0[t] = s.z0[t];
+    z1[t] = s.z1[t];
+  }
+}
+
 template <int WIDTH>
 struct Ctx {
   static constexpr int K = Family<WIDTH>::K;
@@ -848,7 +1099,7 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
 // of level 0.  Called by the whole wave (nv uniform).
 template <int WIDTH, int B, bool ROOTS>
 __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
-                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B]) {
+                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B], lds_u8* stage) {
   using Ly = Layout<WIDTH, B>;
   using Gm = Geo<B>;
   constexpr int K = Family<WIDTH>::K;
@@ -866,6 +1117,14 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
 #pragma unroll
   for (int t = 0; t < K; ++t) s0[t] = s1[t] = 0;
   const uint32_t steps = (nv + Gm::G - 1) / Gm::G;
+  // step e's region: the contiguous executions p + G e .. p + G e + G - 1
+  // (fewer in the last step)
+  auto nq_of = [&](uint32_t e) {
+    return nv - Gm::G * e < (uint32_t)Gm::G ? nv - Gm::G * e : (uint32_t)Gm::G;
+  };
+  auto base_of = [&](uint32_t e) { return str + (p + (uint64_t)Gm::G * e) * XB; };
+  stage_first<WIDTH, B>(base_of(0), (uint32_t)XB, nq_of(0), 0, stage);
+  uint4 xc[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1];  // (no carried blocks here)
   for (uint32_t e = 0; e < steps; ++e) {
     const uint32_t i = Gm::G * e + (uint32_t)q;  // execution within the pass
     const uint32_t m = Gm::NG2 * e + (uint32_t)h;  // its level-1 node
@@ -874,9 +1133,11 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
     uint64_t t0[K], t1[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) t0[t] = t1[t] = 0;
+    uint64_t z0[K], z1[K];
+    const bool more = e + 1 < steps;
+    region_ehc<WIDTH, B>(stage, base_of(e), (uint32_t)XB, nq_of(e), 0, 0, more ? base_of(e + 1) : str,
+                         more ? nq_of(e + 1) : 0, 0, xc, uniform_keys(c.ent + Ly::ehc), z0, z1);
     if (i < nv) {
-      uint64_t z0[K], z1[K];
-      ehc2<WIDTH, B>(str + (p + i) * XB + 16 * r, uniform_keys(c.ent + Ly::ehc), z0, z1);
       if (node_full) {
 #pragma unroll
         for (int t = 0; t < K; ++t) {
@@ -1082,6 +1343,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ uint64_t ltree[K * NT0];
   __shared__ uint64_t lfin[K * NT0 * B];
   __shared__ uint64_t ltail[NTAIL];
+  // this wave's region of staged executions
+  __shared__ __attribute__((aligned(1024))) uint8_t stage_buf[Parts<WIDTH, B>::BYTES];
+  lds_u8* const stage = (lds_u8*)stage_buf;
 
   const int lane = threadIdx.x;
   const int q = lane / Gm::LPB, r = lane % Gm::LPB;
@@ -1190,7 +1454,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           }
         }
       }
-      if (N) partial_pass<WIDTH, B, ROOTS>(c, str, 0, (uint32_t)N, F, lacc);
+      if (N) partial_pass<WIDTH, B, ROOTS>(c, str, 0, (uint32_t)N, F, lacc, stage);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
@@ -1206,21 +1470,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     } else {
       const uint64_t g0 = tau * texec;
       const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
+      // the first region of a first full pass is copied ahead
+      constexpr uint32_t QS = 8 * (uint32_t)XB;  // lane group stride of a full pass's region
+      if (N - g0 >= (uint64_t)Gm::PASS) stage_first<WIDTH, B>(str + g0 * XB, QS, Gm::G, 0, stage);
+      uint4 xc[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1];  // blocks carried between regions
       for (uint64_t p = g0; p < g1; p += Gm::PASS) {
         if (N - p < Gm::PASS) {
           // the string's last, partial pass
-          partial_pass<WIDTH, B, ROOTS>(c, str, p, (uint32_t)(N - p), F, lacc);
+          partial_pass<WIDTH, B, ROOTS>(c, str, p, (uint32_t)(N - p), F, lacc, stage);
           break;
         }
         // full pass: lane group q takes the 8 consecutive executions
-        // p + 8q .. p + 8q + 7, i.e. all children of level-1 node p/8 + q
+        // p + 8q .. p + 8q + 7, i.e. all children of level-1 node p/8 + q;
+        // region e holds executions p + 8q + e of every lane group
         uint64_t a0[K], a1[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
-        const uint8_t* col = str + (p + 8 * q) * XB + 16 * r;
+        // the next pass is a full pass of this task: its first region is
+        // copied during this pass's last step (uniform)
+        const bool next_full = p + Gm::PASS < g1 && N - (p + Gm::PASS) >= (uint64_t)Gm::PASS;
         for (int e = 0; e < 8; ++e) {
+          const uint8_t* next = e < 7 ? str + (p + e + 1) * XB : str + (p + Gm::PASS) * XB;
+          const uint32_t nnq = e < 7 || next_full ? (uint32_t)Gm::G : 0;
+          const uint32_t cin = e > 0 ? carry_blocks<WIDTH, B>(str, p, e - 1) : 0;
+          const uint32_t cout = carry_blocks<WIDTH, B>(str, p, e);
           uint64_t z0[K], z1[K];
-          ehc2<WIDTH, B>(col + e * XB, uniform_keys(ent + Ly::ehc), z0, z1);
+          region_ehc<WIDTH, B>(stage, str + (p + e) * XB, QS, Gm::G, cin, cout, next, nnq, e < 7 ? cout : 0, xc,
+                               uniform_keys(ent + Ly::ehc), z0, z1);
           // level 0 of every tree: child e of this lane's level-1 node
           if (e < kFan - 1) {
 #pragma unroll
