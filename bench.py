@@ -408,6 +408,12 @@ def run_uneven(args):
     n = torch.from_numpy(lens.view(np.int64)).to(dev)
     seed = hth.expand_seed(3)
     hth.reserve(count)
+    if args.calibration_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.no_autotune:
         choice, times = (0, 0, 5), {}
         hth.set_tuning(width)

@@ -249,10 +249,11 @@ hth_status hth_batch_check(hipStream_t stream);
 
 /* Diagnostic: a plain streaming read of `bytes` (rounded down to 16-byte
    pieces) of the device buffer buf (16-byte aligned), the achievable HBM
-   read rate that the hashing kernel is measured against.  Runs 8 waves per
-   compute unit (two workgroups of 256 threads; the rate is highest there),
-   at most one workgroup per word of the device array sink (sink_words >= 1;
-   its words are XOR-ed with the data read, so the caller zeroes it first).
+   read rate that the hashing kernel is measured against.  Each single-wave
+   workgroup reads a contiguous share with non-temporal 16-byte loads, 4
+   workgroups per compute unit (the rate is highest there), at most one
+   workgroup per word of the device array sink (sink_words >= 1; its words
+   are XOR-ed with the data read, so the caller zeroes it first).
    Enqueued on `stream`.  Errors: HTH_E_INVALID, HTH_E_HIP. */
 hth_status hth_read_probe(const void *buf, uint64_t bytes, uint64_t *sink, uint32_t sink_words,
                           hipStream_t stream);

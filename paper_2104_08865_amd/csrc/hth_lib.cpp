@@ -527,8 +527,8 @@ hth_status hth_read_probe(const void* buf, uint64_t bytes, uint64_t* sink, uint3
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "device attribute");
-  // 8 waves per compute unit (2 workgroups of 4 waves): the rate peaks there
-  uint32_t blocks = (uint32_t)cus * 2;
+  // 4 single-wave workgroups per compute unit: the rate peaks there
+  uint32_t blocks = (uint32_t)cus * 4;
   if (blocks > sink_words) blocks = sink_words;
   e = hth::launch_read_probe(buf, bytes / 16, sink, blocks, stream);
   if (e != hipSuccess) return hip_fail(e, "read probe launch");
