@@ -18,6 +18,12 @@ Extra objects on the JSON line:
   cpu_baseline  the CPU oracle on this host, single-threaded, on a bounded
                 sample of the same batch; the sample is also checked
                 bit-for-bit against the GPU output.
+  uneven        the uneven batch (200,521 strings of 0 B - 256 KiB, width 24):
+                one persistent launch per step, the same launch replayed from
+                a HIP graph, and one launch per string on a stated sample of
+                strings; its own roofline, traffic and CPU baseline.
+  latency       the serving loop: capacity, then p50/p99 at three offered
+                loads; 1.6 % of the served results recomputed by the oracle.
 
   python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
   python bench.py --workload uneven   # 200,521 strings of 16 B - 256 KiB, width 24:
@@ -139,6 +145,7 @@ def run_main():
     ap.add_argument("--workload", choices=("throughput", "uneven", "long", "serve", "compose"), default="throughput")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per offered load (serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg of the default line")
     ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default launch choice")
     ap.add_argument("--block-words", type=int, default=8, choices=(4, 8),
                     help="throughput workload: the family's block size b (8, or 4 for the 256-bit family)")
@@ -283,9 +290,11 @@ def run_throughput(args):
         "per_width": per_width,
         "cpu_baseline": cpu,
     }
+    del data, outs
+    torch.cuda.empty_cache()
+    if not args.no_uneven:
+        line["uneven"] = uneven_leg(args)
     if not args.no_serve:
-        del data, outs
-        torch.cuda.empty_cache()
         line["latency"] = serve_legs(args.serve_requests)
     return line
 
@@ -320,6 +329,7 @@ def serve_legs(n_req, verify=False):
         # capacity: every request due at once
         tickets = srv.replay(data, offs, lens, widths, np.zeros(n_req, dtype=np.uint64), threads=SERVE_CLIENTS)
         got = srv.wait_many(tickets)
+        res["oracle_spot_check"] = _serve_spot_check(data, offs, lens, widths, got)
         st = srv.stats()
         cap_rps = st["completed"] / st["elapsed_s"]
         res["capacity"] = {"requests_per_s": cap_rps, "GBps": st["gbps"], "p50_us": st["latency_p50_us"],
@@ -356,6 +366,32 @@ def serve_legs(n_req, verify=False):
     return res
 
 
+SERVE_SPOT_STRIDE = 64  # every 64th request (1.6 %) is recomputed by the oracle
+
+
+def _serve_spot_check(data, offs, lens, widths, got):
+    """Every SERVE_SPOT_STRIDE-th served result against the CPU oracle (all
+    host cores; a verification aid, not a timing)."""
+    import oracle
+    from paper_2104_08865_amd import workloads as wl
+    ent = oracle.expand_seed(5)
+    idx = np.arange(0, lens.size, SERVE_SPOT_STRIDE)
+    exact = True
+    t0 = time.perf_counter()
+    for w in (16, 40):
+        sel = idx[widths[idx] == w]
+        sub_lens = lens[sel]
+        sub_offs, _ = wl.pack(sub_lens)
+        sub = np.concatenate([data[int(offs[i]):int(offs[i]) + int(lens[i])] for i in sel])
+        ref = oracle.hash_batch(ent, sub, sub_offs, sub_lens, w, nthreads=min(16, os.cpu_count() or 1))
+        exact &= bool((got[sel, :w] == ref).all())
+    dt = time.perf_counter() - t0
+    log(f"[bench] serving oracle spot check: {idx.size} requests, exact={exact} ({dt:.1f} s)")
+    return {"requests": int(idx.size), "fraction": idx.size / lens.size,
+            "sample": f"every {SERVE_SPOT_STRIDE}th request of the capacity run, recomputed by the CPU oracle",
+            "bit_exact": exact}
+
+
 def run_serve(args):
     """Serving workload line: value = served GB/s at capacity."""
     import torch
@@ -388,12 +424,24 @@ def _timed_launches(hth, torch, launch, steps):
     return time.perf_counter() - t0
 
 
+UNEVEN_PER_STRING_SAMPLE = 4096  # strings launched one by one in the default line's uneven leg
+
+
 def run_uneven(args):
     """200,000 log-uniform lengths in [16 B, 256 KiB) plus every length 0..520
     (bytes from splitmix64 seed 3, packed back to back, so most strings start
     unaligned), width 24."""
+    leg = uneven_leg(args, autotune=not args.no_autotune, per_string=None if not args.no_per_string else 0)
+    return _uneven_line(args, leg)
+
+
+def uneven_leg(args, autotune=False, per_string=UNEVEN_PER_STRING_SAMPLE):
+    """The uneven batch: one persistent launch per step (timed over args.steps),
+    the same launch replayed from a HIP graph, and one launch per string --
+    for every string (per_string None), a stated sample of strings spread over
+    the batch (per_string > 0) or none (0).  Returns the leg's figures."""
     import torch
-    from paper_2104_08865_amd import autotune, hth
+    from paper_2104_08865_amd import autotune as at, hth
     from paper_2104_08865_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -414,12 +462,12 @@ def run_uneven(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.no_autotune:
+    if not autotune:
         choice, times = (0, 0, 5), {}
         hth.set_tuning(width)
     else:
-        choice, times = autotune.tune(seed, data, o, n, width, total_bytes=total, use_cache=False)
-    log(f"[bench] autotuned launch choice (waves/CU, min level, max level) = {choice}")
+        choice, times = at.tune(seed, data, o, n, width, total_bytes=total, use_cache=False)
+    log(f"[bench] uneven launch choice (waves/CU, min level, max level) = {choice}")
     out = torch.empty((count, width), dtype=torch.uint8, device=dev)
 
     # one persistent launch per step
@@ -441,31 +489,73 @@ def run_uneven(args):
     g.check()
     graph_out = g.out.cpu().numpy()
 
-    if args.no_per_string:
-        swall, per_out = None, persistent
+    # one launch per string
+    if per_string == 0:
+        sidx, swall, sbytes, per_out = None, None, None, None
     else:
-        swall, per_out = _per_string(hth, torch, seed, data, o, n, width, count, dev)
-    agree = bool((persistent == graph_out).all() and (persistent == per_out).all())
-    pstr = f"{total / swall / 1e9:.1f}" if swall else "skipped"
+        sidx = np.arange(count) if per_string is None else np.linspace(0, count - 1, per_string).astype(np.int64)
+        swall, per_out = _per_string(hth, torch, seed, data, o, n, width, sidx, dev)
+        sbytes = int(lens[sidx].sum())
+    agree = bool((persistent == graph_out).all() and (per_out is None or (persistent[sidx] == per_out).all()))
+    pstr = f"{sbytes / swall / 1e9:.2f}" if swall else "skipped"
     log(f"[bench] persistent {total / wall * args.steps / 1e9:.0f} GB/s, graph {total / gwall * args.steps / 1e9:.0f} "
         f"GB/s, per-string {pstr} GB/s, identical={agree}")
-    return _uneven_line(args, total, count, wall, gwall, swall, kernel_ms, width, choice, times, agree, persistent,
-                        lens, offs)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        idx = np.arange(0, count, 20)
+        sub_lens = lens[idx]
+        sub_offs, sub_total = wl.pack(sub_lens)
+        sub = np.concatenate([wl.random_bytes(3, int(lens[i]), start_byte=int(offs[i])) for i in idx])
+        ent = oracle.expand_seed(3)
+        ref, dt, core = pinned_oracle(lambda: oracle.hash_batch(ent, sub, sub_offs, sub_lens, width, nthreads=1))
+        cpu = {"value": sub_total / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"every 20th string of the batch ({idx.size} strings, {sub_total} bytes), "
+                         f"single thread pinned to core {core}",
+               "seconds": dt, "bit_exact_vs_gpu": bool((ref == persistent[idx]).all())}
+        log(f"[bench] uneven cpu oracle: {idx.size} strings in {dt:.1f} s, exact={cpu['bit_exact_vs_gpu']}")
+    del data, out, g
+    torch.cuda.empty_cache()
+
+    algo = total + 16 * count + width * count
+    persistent_gbps = total * args.steps / wall / 1e9
+    per_gbps = sbytes / swall / 1e9 if swall else None
+    return {
+        "workload": "uneven batch: 200,000 log-uniform lengths in [16 B, 256 KiB) plus every length 0..520, "
+                    "packed back to back (splitmix64 seed 3), width 24",
+        "strings": int(count), "bytes": int(total), "width": width, "seed": 3,
+        "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]},
+        "steps": args.steps, "ms_per_step": wall / args.steps * 1e3,
+        "persistent_GBps": persistent_gbps,
+        "roofline": _roofline(f"hth::hash_main_kernel<{width}, 8, false>", algo, kernel_ms,
+                              measured_traffic(width, UNEVEN_TRAFFIC_FILE) if choice in DEFAULT_CHOICES else None),
+        "graph_replay_GBps": total * args.steps / gwall / 1e9,
+        "per_string_launches_GBps": per_gbps,
+        "per_string_sample": None if sidx is None else
+            (f"all {count} strings" if per_string is None else
+             f"{sidx.size} strings spread evenly over the batch ({sbytes} bytes), one hth_hash_batch call each"),
+        "persistent_over_per_string": persistent_gbps / per_gbps if per_gbps else None,
+        "all_identical": agree,
+        "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
+        "cpu_baseline": cpu,
+    }
 
 
-def _per_string(hth, torch, seed, data, o, n, width, count, dev):
-    """The same library call once per string (one launch each)."""
+def _per_string(hth, torch, seed, data, o, n, width, idx, dev):
+    """The same library call once per string of the index sample idx (one
+    launch each); returns the wall time and their outputs."""
     import ctypes
     L = hth.lib()
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    per = torch.empty((count, width), dtype=torch.uint8, device=dev)
+    per = torch.empty((idx.size, width), dtype=torch.uint8, device=dev)
     sp, dp, op, np_, pp = seed.handle, ctypes.c_void_p(data.data_ptr()), o.data_ptr(), n.data_ptr(), per.data_ptr()
-    log("[bench] per-string launches ...")
+    log(f"[bench] per-string launches ({idx.size} strings) ...")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(count):
+    for k, i in enumerate(idx.tolist()):
         rc = L.hth_hash_batch(sp, dp, ctypes.c_void_p(op + 8 * i), ctypes.c_void_p(np_ + 8 * i), 1,
-                              ctypes.c_void_p(pp + width * i), width, stream)
+                              ctypes.c_void_p(pp + width * k), width, stream)
         if rc:
             raise RuntimeError(L.hth_last_error())
     torch.cuda.synchronize()
@@ -473,42 +563,23 @@ def _per_string(hth, torch, seed, data, o, n, width, count, dev):
     return swall, per.cpu().numpy()
 
 
-def _uneven_line(args, total, count, wall, gwall, swall, kernel_ms, width, choice, times, agree, persistent, lens,
-                 offs):
-    import oracle
-    from paper_2104_08865_amd import workloads as wl
-    cpu = None
-    if not args.no_cpu_baseline:
-        idx = np.arange(0, count, 20)
-        sub_lens = lens[idx]
-        sub_offs, sub_total = wl.pack(sub_lens)
-        sub = np.concatenate([wl.random_bytes(3, int(lens[i]), start_byte=int(offs[i])) for i in idx])
-        ent = oracle.expand_seed(3)
-        t0 = time.perf_counter()
-        ref = oracle.hash_batch(ent, sub, sub_offs, sub_lens, width, nthreads=1)
-        dt = time.perf_counter() - t0
-        cpu = {"value": sub_total / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"every 20th string of the batch ({idx.size} strings, {sub_total} bytes), single thread",
-               "seconds": dt, "bit_exact_vs_gpu": bool((ref == persistent[idx]).all())}
-
-    algo = total + 16 * count + width * count
+def _uneven_line(args, leg):
     return {
         "metric": "hashed GB/s vs HBM peak (bit-exact to oracle); p50/p99 latency at fixed rate",
-        "value": total * args.steps / wall / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "value": leg["persistent_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "uneven batch: 200,000 log-uniform lengths in [16 B, 256 KiB) plus every length "
-                               "0..520, packed back to back (splitmix64 seed 3), width 24, one persistent launch",
-                   "strings": int(count), "bytes": int(total), "width": width, "seed": 3,
-                   "launch_choice": {"waves_per_cu": choice[0], "task_levels": [choice[1], choice[2]]}},
-        "roofline": _roofline(f"hth::hash_main_kernel<{width}, 8, false>", algo, kernel_ms,
-                              measured_traffic(width, UNEVEN_TRAFFIC_FILE) if choice in DEFAULT_CHOICES else None),
-        "graph_replay_GBps": total * args.steps / gwall / 1e9,
-        "per_string_launches_GBps": total / swall / 1e9 if swall else None,
-        "persistent_over_per_string": (total * args.steps / wall) / (total / swall) if swall else None,
-        "all_three_identical": agree,
-        "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
-        "cpu_baseline": cpu,
+        "config": {"workload": leg["workload"] + ", one persistent launch", "strings": leg["strings"],
+                   "bytes": leg["bytes"], "width": leg["width"], "seed": leg["seed"],
+                   "launch_choice": leg["launch_choice"]},
+        "roofline": leg["roofline"],
+        "graph_replay_GBps": leg["graph_replay_GBps"],
+        "per_string_launches_GBps": leg["per_string_launches_GBps"],
+        "per_string_sample": leg["per_string_sample"],
+        "persistent_over_per_string": leg["persistent_over_per_string"],
+        "all_three_identical": leg["all_identical"],
+        "autotune_ms": leg["autotune_ms"],
+        "cpu_baseline": leg["cpu_baseline"],
     }
 
 

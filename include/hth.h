@@ -232,7 +232,7 @@ hth_status hth_batch_graph_free(hth_batch_graph *graph);
    different streams, or different host threads without ordering) race and
    give wrong values.  Order them on one stream. */
 #define HTH_NOALLOC_MAX_COUNT 65536
-#define HTH_NOALLOC_SCRATCH_BYTES 7122944
+#define HTH_NOALLOC_SCRATCH_BYTES 7386112
 hth_status hth_hash_batch_noalloc(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
                                   const uint64_t *lengths, uint64_t count, uint8_t *out, uint32_t out_width,
                                   hipStream_t stream);

@@ -33,6 +33,7 @@ struct Workspace {
   uint32_t* acc_start = nullptr;
   uint32_t* bucket_lead = nullptr;
   uint32_t* tiny_list = nullptr;
+  uint32_t* small_list = nullptr;
   uint64_t* sacc = nullptr;
   uint32_t* sdone = nullptr;
   uint64_t* gacc = nullptr;
@@ -72,6 +73,11 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
                          const uint64_t* lengths, uint64_t count, uint8_t* out, uint32_t out_width, Workspace& w,
                          hipStream_t stream, hipEvent_t main_start, hipEvent_t main_stop, uint64_t max_waves = 0,
                          uint64_t* roots = nullptr, uint32_t direct_lim = 0);
+
+// Grids of the tail-only and small-string kernels for a batch of `count`
+// strings (cached occupancy queries).
+hth_status tiny_grid_for(uint32_t width, uint32_t block, uint64_t count, uint32_t* grid);
+hth_status small_grid_for(uint32_t width, uint32_t block, uint64_t count, uint32_t* grid);
 
 // Upper bound of the tasks a string of `len` bytes can make (at the finest
 // task size) in the family with `block` words per block, for max_waves.

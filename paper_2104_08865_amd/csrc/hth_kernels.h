@@ -20,12 +20,21 @@ constexpr uint32_t kMaxBuckets = 1u << 16;
 constexpr uint64_t kMinBucketBytes = 128u << 10;
 constexpr uint64_t kTaskOverheadBytes = 4096;
 constexpr int kPlanSums = 3;  // per candidate task size: tasks, accumulators, work
-// Per planner block: kPlanSums per candidate, then the block's tail-only strings.
-constexpr int kBlockSums = kPlanCandidates * kPlanSums + 1;
+// Per planner block: kPlanSums per candidate, then the block's tail-only and
+// small strings.
+constexpr int kSumTiny = kPlanCandidates * kPlanSums;
+constexpr int kSumSmall = kSumTiny + 1;
+constexpr int kBlockSums = kSumSmall + 1;
+// Per-block prefixes of the chosen level: tasks, accumulators, work, tail-only
+// and small strings.
+constexpr int kPlanPre = kPlanSums + 2;
 // Tail-only strings (shorter than one EHC execution) get no task: they are
 // listed apart and hashed one string per lane, in chunks of kTinyChunk
 // strings; wave w of the tail-only kernel takes chunks w, w + grid, ...
+// Small strings (1 .. kSmallMax executions: no tree node is complete) get no
+// task either: listed apart, one per half-wave of the small-string kernel.
 constexpr int kTinyChunk = 64;
+constexpr uint32_t kSmallMax = 7;
 // Plans of more planner blocks than this get the scan kernel between their
 // two steps (linear in the block count); smaller ones sum in the fill step.
 constexpr uint32_t kPlanScanMin = 256;
@@ -40,6 +49,7 @@ enum {
   kCtlTiny,      // number of tail-only strings
   kCtlBucketLo,  // bucket size in work bytes (low, high word), for the fill step
   kCtlBucketHi,
+  kCtlSmall,     // number of small strings
   kCtlWords = 16
 };
 
@@ -49,8 +59,9 @@ struct PlanArgs {
   uint32_t exec_bytes;
   uint32_t pass_log2;     // log2 of the executions of one pass (7 for b = 8, 8 for b = 4)
   uint32_t direct_lim;    // strings shorter than this are not hashed at all (0: every string is)
+  uint32_t small_max;     // strings of 1 .. small_max executions are listed as small (0: none)
   uint64_t* block_sums;  // [kBlockSums][nblocks] (column-major)
-  uint64_t* block_pre;   // [kPlanSums + 1][nblocks]: per-block prefixes (large plans)
+  uint64_t* block_pre;   // [kPlanPre][nblocks]: per-block prefixes (large plans)
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
@@ -59,6 +70,7 @@ struct PlanArgs {
   uint32_t* acc_start;    // [count]
   uint32_t* bucket_lead;  // [kMaxBuckets]: leader task of each bucket, any order
   uint32_t* tiny_list;    // [count]: the tail-only strings
+  uint32_t* small_list;   // [count]: the small strings
   uint32_t* ctl;          // [kCtlWords]
 };
 
@@ -77,6 +89,7 @@ struct MainArgs {
   uint32_t* gcnt;  // [cap_accs], zero between launches
   const uint32_t* bucket_lead;
   const uint32_t* tiny_list;
+  const uint32_t* small_list;
   uint64_t* roots;  // root mode only: [count][kMaxK * 8]
   uint32_t* ctl;
 };
@@ -92,10 +105,11 @@ uint64_t plan_block_count(uint64_t count);
 hipError_t launch_read_probe(const void* buf, uint64_t n16, uint64_t* sink, uint32_t blocks, hipStream_t stream);
 hipError_t launch_plan(const PlanArgs& p, hipStream_t stream);
 // The hashing kernel with `grid` waves, then the tail-only kernel with
-// `tiny_grid` waves.
+// `tiny_grid` waves and the small-string kernel with `small_grid` waves.
 hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, uint32_t tiny_grid,
-                       hipStream_t stream);
+                       uint32_t small_grid, hipStream_t stream);
 const void* tiny_kernel_fn(uint32_t width, uint32_t block);
+const void* small_kernel_fn(uint32_t width, uint32_t block);
 
 // Composition with simple tabulation: one string per thread; the string's
 // key is its own bytes (lengths <= width) or its HalftimeHash value in h.

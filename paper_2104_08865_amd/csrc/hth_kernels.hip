@@ -238,6 +238,21 @@ __device__ __forceinline__ void ehc2(const uint8_t* __restrict__ eb, key_ptr S_e
 // Planning kernels: tasks and cross-task accumulators per string.
 // ---------------------------------------------------------------------------
 
+// Strings of at most small_max executions get no task: tail-only strings (no
+// execution) and small strings are listed apart, each kind hashed by a kernel
+// of its own; tasks are counted from the executions of the other strings.
+__device__ __forceinline__ uint64_t task_execs(uint64_t L, uint32_t exec_bytes, uint32_t small_max) {
+  const uint64_t N = L / exec_bytes;
+  return N <= small_max ? 0 : N;
+}
+__device__ __forceinline__ bool tail_only(uint64_t L, uint32_t exec_bytes, uint32_t direct_lim) {
+  return L < exec_bytes && L >= direct_lim;
+}
+__device__ __forceinline__ bool small_string(uint64_t L, uint32_t exec_bytes, uint32_t small_max) {
+  const uint64_t N = L / exec_bytes;
+  return N >= 1 && N <= small_max;
+}
+
 // Per string and per candidate task size 2^pass_log2 * 8^j executions (a
 // pass is 128 executions for b = 8, 256 for b = 4): number of tasks, and
 // number of cross-task accumulators (complete nodes of levels >= j + 3).
@@ -348,11 +363,11 @@ __device__ void block_exclusive_n(uint64_t (&v)[NV], uint64_t (*lds)[NV], uint64
 // `v` receives the workgroup's sums (every thread) and `L` this thread's
 // lengths; the sums also go to column blk of block_sums unless it is null.
 __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count,
-                                uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim,
+                                uint32_t exec_bytes, uint32_t pass_log2, uint32_t direct_lim, uint32_t small_max,
                                 uint64_t* __restrict__ block_sums, uint32_t* __restrict__ ctl,
                                 uint64_t (&v)[kBlockSums], uint64_t (&L)[kPlanPer]) {
   __shared__ uint64_t lds[kPlanWaves][kBlockSums];
-  __shared__ uint64_t lds1[kPlanWaves][1];
+  __shared__ uint64_t lds1[kPlanWaves][2];
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
@@ -361,20 +376,24 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
     L[i] = base + i < count ? lengths[base + i] : 0;
-    N[i] = L[i] / exec_bytes;
+    N[i] = task_execs(L[i], exec_bytes, small_max);
     any |= N[i] != 0;
   }
 #pragma unroll
   for (int k = 0; k < kBlockSums; ++k) v[k] = 0;
-  uint64_t tiny = 0;
+  uint64_t tiny = 0, small = 0;
 #pragma unroll
-  for (int i = 0; i < kPlanPer; ++i) tiny += base + i < count && N[i] == 0 && L[i] >= direct_lim;
-  // a block of tail-only strings (common in batches of short keys) has no
-  // tasks at any level: only its tail-only count is summed
+  for (int i = 0; i < kPlanPer; ++i) {
+    tiny += base + i < count && tail_only(L[i], exec_bytes, direct_lim);
+    small += base + i < count && small_string(L[i], exec_bytes, small_max);
+  }
+  // a block of listed strings only (common in batches of short keys) has no
+  // tasks at any level: only its listed counts are summed
   if (!__syncthreads_or(any)) {
-    uint64_t t1[1] = {tiny};
+    uint64_t t1[2] = {tiny, small};
     block_sum_n(t1, lds1);
-    v[kBlockSums - 1] = t1[0];
+    v[kSumTiny] = t1[0];
+    v[kSumSmall] = t1[1];
   } else {
 #pragma unroll
     for (int j = 0; j < kPlanCandidates; ++j) {
@@ -391,7 +410,8 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
       v[j * kPlanSums + 1] = a;
       v[j * kPlanSums + 2] = w;
     }
-    v[kBlockSums - 1] = tiny;
+    v[kSumTiny] = tiny;
+    v[kSumSmall] = small;
     block_sum_n(v, lds);
   }
   // (column-major, [kBlockSums][nblocks]: the steps that read a column over
@@ -445,7 +465,8 @@ __device__ void plan_choose(const uint64_t (&tot)[kBlockSums], uint64_t cap_task
     ctl[kCtlTotal] = (uint32_t)ntasks;
     ctl[kCtlLevel] = jsel >= 0 ? (uint32_t)jsel : 0;
     ctl[kCtlError] = jsel >= 0 ? 0 : 1;
-    ctl[kCtlTiny] = jsel >= 0 ? (uint32_t)tot[kBlockSums - 1] : 0;
+    ctl[kCtlTiny] = jsel >= 0 ? (uint32_t)tot[kSumTiny] : 0;
+    ctl[kCtlSmall] = jsel >= 0 ? (uint32_t)tot[kSumSmall] : 0;
     ctl[kCtlBucketLo] = (uint32_t)bucket;
     ctl[kCtlBucketHi] = (uint32_t)(bucket >> 32);
   }
@@ -466,15 +487,16 @@ enum { kFillSum = 0, kFillPre = 1, kFillSingle = 2 };
 template <int MODE>
 __device__ void plan_fill_body(
     uint32_t blk, const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
+    uint32_t direct_lim, uint32_t small_max, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
     const uint64_t* __restrict__ block_pre, const uint64_t (&tot_in)[kBlockSums],
     const uint64_t (&len_in)[kPlanPer], uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
-    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ small_list, uint32_t* __restrict__ ctl) {
   __shared__ uint64_t lds[kPlanWaves];
   __shared__ uint64_t ldsn[kPlanWaves][kBlockSums];
-  __shared__ uint64_t lds4[kPlanWaves][kPlanSums + 1];
+  __shared__ uint64_t lds4[kPlanWaves][kPlanPre];
+  __shared__ uint64_t lds2[kPlanWaves][2];
   __shared__ uint64_t lds3[kPlanWaves][kPlanSums];
   __shared__ uint32_t incl[kPlanBlock];
   __shared__ uint64_t wstart[kPlanBlock];
@@ -482,7 +504,7 @@ __device__ void plan_fill_body(
   const int tid = threadIdx.x;
   int jsel;
   uint64_t bucket;
-  uint64_t pre[kPlanSums + 1] = {0, 0, 0, 0};
+  uint64_t pre[kPlanPre] = {0, 0, 0, 0, 0};
   if constexpr (MODE == kFillSingle) {
     plan_choose(tot_in, cap_tasks, cap_accs, min_j, max_j, target_tasks, tid == 0, ctl, jsel, bucket);
     if (jsel < 0) return;  // uniform over the workgroup
@@ -491,7 +513,7 @@ __device__ void plan_fill_body(
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
 #pragma unroll
-    for (int k = 0; k <= kPlanSums; ++k) pre[k] = block_pre[(uint64_t)k * nblocks + blk];
+    for (int k = 0; k < kPlanPre; ++k) pre[k] = block_pre[(uint64_t)k * nblocks + blk];
   } else {
     // Totals of every candidate over all blocks (threads stride over blocks).
     uint64_t tot[kBlockSums];
@@ -507,7 +529,8 @@ __device__ void plan_fill_body(
     for (uint32_t b = tid; b < blk; b += kPlanThreads) {
 #pragma unroll
       for (int k = 0; k < kPlanSums; ++k) pre[k] += block_sums[(uint64_t)(jsel * kPlanSums + k) * nblocks + b];
-      pre[kPlanSums] += block_sums[(uint64_t)(kBlockSums - 1) * nblocks + b];
+      pre[kPlanSums] += block_sums[(uint64_t)kSumTiny * nblocks + b];
+      pre[kPlanSums + 1] += block_sums[(uint64_t)kSumSmall * nblocks + b];
     }
     block_sum_n(pre, lds4);
   }
@@ -515,33 +538,39 @@ __device__ void plan_fill_body(
   const uint64_t acc_base = pre[1];
   const uint64_t work_base = pre[2];
   const uint64_t tiny_base = pre[3];
+  const uint64_t small_base = pre[4];
 
   const uint64_t base = (uint64_t)blk * kPlanBlock + tid * kPlanPer;
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
-  uint64_t st = 0, sa = 0, sw = 0, sy = 0;
-  bool tiny[kPlanPer];
+  uint64_t st = 0, sa = 0, sw = 0, sy = 0, sm = 0;
+  bool tiny[kPlanPer], small[kPlanPer];
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
     tk[i] = ac[i] = wk[i] = 0;
-    tiny[i] = false;
+    tiny[i] = small[i] = false;
     if (base + i < count) {
       const uint64_t L = MODE == kFillSingle ? len_in[i] : lengths[base + i];
       slen[tid * kPlanPer + i] = L;
-      plan_counts(L / exec_bytes, jsel, pass_log2, tk[i], ac[i]);
+      plan_counts(task_execs(L, exec_bytes, small_max), jsel, pass_log2, tk[i], ac[i]);
       wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
-      tiny[i] = L < exec_bytes && L >= direct_lim;
+      tiny[i] = tail_only(L, exec_bytes, direct_lim);
+      small[i] = small_string(L, exec_bytes, small_max);
     }
     st += tk[i];
     sa += ac[i];
     sw += wk[i];
     sy += tiny[i];
+    sm += small[i];
   }
   const bool any = __syncthreads_or(st != 0) != 0;
-  uint64_t blk_y;
-  uint64_t ty = tiny_base + block_exclusive(sy, lds, blk_y);
+  uint64_t lst[2] = {sy, sm}, blk_l[2];
+  block_exclusive_n(lst, lds2, blk_l);
+  uint64_t ty = tiny_base + lst[0], tm = small_base + lst[1];
 #pragma unroll
-  for (int i = 0; i < kPlanPer; ++i)
+  for (int i = 0; i < kPlanPer; ++i) {
     if (tiny[i]) tiny_list[ty++] = (uint32_t)(base + i);
+    if (small[i]) small_list[tm++] = (uint32_t)(base + i);
+  }
   // a block without tasks (tail-only strings) is done: no task table
   // entries, offsets or bucket leaders (uniform over the workgroup)
   if (!any) return;
@@ -618,10 +647,11 @@ __device__ void plan_fill_body(
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t* __restrict__ lengths,
                                                                   uint64_t count, uint32_t exec_bytes,
                                                                   uint32_t pass_log2, uint32_t direct_lim,
+                                                                  uint32_t small_max,
                                                                   uint64_t* __restrict__ block_sums,
                                                                   uint32_t* __restrict__ ctl) {
   uint64_t v[kBlockSums], L[kPlanPer];
-  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums, ctl, v, L);
+  plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, small_max, block_sums, ctl, v, L);
 }
 
 // Large plans, between the two steps: totals, the task level and bucket
@@ -636,7 +666,7 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
     const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint64_t* __restrict__ block_pre,
     uint32_t* __restrict__ ctl) {
-  constexpr int NP = kPlanSums + 1, NW = kScanThreads / 64;
+  constexpr int NP = kPlanPre, NW = kScanThreads / 64;
   __shared__ uint64_t ldsn[NW][kBlockSums];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t per = (nblocks + NW - 1) / NW;
@@ -661,7 +691,7 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
   uint64_t carry[NP], x[NP][4];
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int c = k < kPlanSums ? jsel * kPlanSums + k : kBlockSums - 1;
+    const int c = k < kPlanSums ? jsel * kPlanSums + k : k == kPlanSums ? kSumTiny : kSumSmall;
     col[k] = block_sums + (uint64_t)c * nblocks;
     carry[k] = wave_sum64(lane < w ? ldsn[lane][c] : 0);  // the earlier waves' blocks
 #pragma unroll
@@ -698,15 +728,16 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
 template <bool PRE>
 __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    uint32_t direct_lim, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
+    uint32_t direct_lim, uint32_t small_max, const uint64_t* __restrict__ block_sums, uint32_t nblocks,
     const uint64_t* __restrict__ block_pre, uint64_t cap_tasks, uint64_t cap_accs,
     uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint32_t* __restrict__ task_string,
     uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start, uint32_t* __restrict__ bucket_lead,
-    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ small_list, uint32_t* __restrict__ ctl) {
   const uint64_t none[kBlockSums] = {}, none_l[kPlanPer] = {};
-  plan_fill_body<PRE ? kFillPre : kFillSum>(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, block_sums,
+  plan_fill_body<PRE ? kFillPre : kFillSum>(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim,
+                                            small_max, block_sums,
                                             nblocks, block_pre, none, none_l, cap_tasks, cap_accs, min_j, max_j,
-                 target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, ctl);
+                 target_tasks, task_string, task_start, acc_start, bucket_lead, tiny_list, small_list, ctl);
 }
 
 // Both steps in one workgroup, for batches of at most kPlanBlock strings
@@ -714,15 +745,17 @@ __global__ __launch_bounds__(kPlanThreads) void plan_fill_kernel(
 // registers (nothing goes through block_sums).
 __global__ __launch_bounds__(kPlanThreads) void plan_single_kernel(
     const uint64_t* __restrict__ lengths, uint64_t count, uint32_t exec_bytes, uint32_t pass_log2,
-    uint32_t direct_lim, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
+    uint32_t direct_lim, uint32_t small_max, uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j,
     uint64_t target_tasks,
     uint32_t* __restrict__ task_string, uint32_t* __restrict__ task_start, uint32_t* __restrict__ acc_start,
-    uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ bucket_lead, uint32_t* __restrict__ tiny_list, uint32_t* __restrict__ small_list,
+    uint32_t* __restrict__ ctl) {
   uint64_t v[kBlockSums], L[kPlanPer];
-  plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, nullptr, ctl, v, L);
-  plan_fill_body<kFillSingle>(0, lengths, count, exec_bytes, pass_log2, direct_lim, nullptr, 1, nullptr, v, L,
+  plan_count_body(0, lengths, count, exec_bytes, pass_log2, direct_lim, small_max, nullptr, ctl, v, L);
+  plan_fill_body<kFillSingle>(0, lengths, count, exec_bytes, pass_log2, direct_lim, small_max, nullptr, 1, nullptr,
+                              v, L,
                               cap_tasks, cap_accs, min_j, max_j, target_tasks, task_string, task_start, acc_start,
-                              bucket_lead, tiny_list, ctl);
+                              bucket_lead, tiny_list, small_list, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,6 +856,15 @@ __device__ __forceinline__ uint32_t part_a_blocks(const uint8_t* at) {
   return P::C0 + ((128u - (a + P::BB * P::C0) % 128u) % 128u) / P::BB;
 }
 
+// This lane's index, opaque to the compiler: per-lane addresses derived from it
+// are recomputed where they are used instead of being hoisted out of the task
+// loop and held in registers for the whole kernel (which spilled).
+__device__ __forceinline__ uint32_t opaque_lane() {
+  uint32_t l = threadIdx.x;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 // Waits for this wave's outstanding vector memory operations (the copies into
 // LDS among them: vmcnt(0)), or for its LDS reads and scalar loads
 // (lgkmcnt(0)); the other counters are left at their maximum (gfx9 encoding:
@@ -848,10 +890,7 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
   constexpr uint32_t FIRST = PART_B ? P::C0 : 0;  // block at slot position 0
   // copied bytes of a slot: [wlo, whi) (uniform when UNI)
   const uint32_t ca_u = UNI ? part_a_blocks<WIDTH, B>(base) : 0;
-  // (opaque to the compiler, so that the per-lane offsets are recomputed at
-  // every copy instead of being held in registers)
-  uint32_t lane = threadIdx.x;
-  asm volatile("" : "+v"(lane));
+  const uint32_t lane = opaque_lane();
 #pragma unroll
   for (int i = 0; i < (int)S; ++i) {
     const uint32_t o = 1024u * i + 16u * lane;
@@ -868,7 +907,8 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
 // This lane's instance pair of N blocks of its execution's slot (S blocks).
 template <int B, int N, int S>
 __device__ __forceinline__ void read_slot(const lds_u8* stage, uint4 (&x)[N]) {
-  const int q = threadIdx.x / Geo<B>::LPB, r = threadIdx.x % Geo<B>::LPB;
+  const uint32_t lane = opaque_lane();
+  const int q = lane / Geo<B>::LPB, r = lane % Geo<B>::LPB;
   const lds_u8* at = stage + q * (S * 8 * B) + 16 * r;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -902,31 +942,39 @@ __device__ __forceinline__ uint32_t carry_blocks(const uint8_t* str, uint64_t p,
 // EHC of this lane's execution of a region whose part A is being copied (as
 // stage_first, skipping cin blocks that are in xc); part B also copies the
 // first cout blocks of every execution's successor, which go to xc for the
-// next region.  `next` (nnq > 0) is the next region, whose part A (skipping
-// ncin blocks) is copied while part B of this one is hashed.  Lanes whose
+// next region.  `next` is the next region (part A skipping ncin blocks, or
+// whole), copied while part B of this one is hashed.  Lanes whose
 // execution is past nq hash stale bytes (their results are not used).  Called
-// by the whole wave; cin, cout, ncin uniform, at most LB - 1.
+// by the whole wave; cin, cout, ncin uniform, at most LB - 1.  UNI: a full
+// pass's region (see stage_part).  `hook` (when call_hook, uniform) runs once
+// part A has been read and part B's copy issued.
+struct NextStage;
 template <int WIDTH, int B>
+__device__ __forceinline__ void stage_issue(const NextStage& n, uint32_t cin, lds_u8* stage);
+
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+template <int WIDTH, int B, bool UNI, class Hook = NoHook>
 __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, uint32_t qs, uint32_t nq,
-                                           uint32_t cin, uint32_t cout, const uint8_t* next, uint32_t nnq,
-                                           uint32_t ncin, uint4 (&xc)[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1],
-                                           key_ptr S_ehc, uint64_t z0[], uint64_t z1[]) {
+                                           uint32_t cin, uint32_t cout, const NextStage& next, uint32_t ncin,
+                                           uint4 (&xc)[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1],
+                                           key_ptr S_ehc, uint64_t z0[], uint64_t z1[], const Hook& hook = Hook(),
+                                           bool call_hook = false) {
   using P = Parts<WIDTH, B>;
   constexpr int LX = P::LX;  // blocks C0 .. C0+LX-1 may come from either part
-  const bool uni = qs == 8u * Layout<WIDTH, B>::exec_bytes;  // a full pass's region
   Ehc<WIDTH> s;
   ehc_begin(s);
-  const uint32_t ca = part_a_blocks<WIDTH, B>(base + (threadIdx.x / Geo<B>::LPB) * qs);
+  const uint32_t ca = part_a_blocks<WIDTH, B>(base + (opaque_lane() / Geo<B>::LPB) * qs);
   uint4 xe[LX > 0 ? LX : 1];  // part A's copies of blocks C0 .. C0+LX-1
   {
     uint4 x[P::NA];
     wait_vm();
     read_slot<B, P::NA, P::SA>(stage, x);
     wait_lgkm();
-    if (uni)
-      stage_part<WIDTH, B, true, true>(base, qs, nq, cout, stage);
-    else
-      stage_part<WIDTH, B, true, false>(base, qs, nq, cout, stage);
+    stage_part<WIDTH, B, true, UNI>(base, qs, nq, cout, stage);
+    if (call_hook) hook();  // (e.g. the string's tail loads, in flight with part B)
 #pragma unroll
     for (int k = 0; k < LX; ++k) xe[k] = x[P::C0 + k];
 #pragma unroll
@@ -939,12 +987,7 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
     wait_vm();
     read_slot<B, P::NB, P::SB>(stage, x);
     wait_lgkm();
-    if (nnq) {
-      if (uni)
-        stage_part<WIDTH, B, false, true>(next, qs, nnq, ncin, stage);
-      else
-        stage_part<WIDTH, B, false, false>(next, qs, nnq, ncin, stage);
-    }
+    stage_issue<WIDTH, B>(next, ncin, stage);
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
       if ((uint32_t)(P::C0 + k) < ca) x[k] = xe[k];
@@ -958,6 +1001,50 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
     z0[t] = s.z0[t];
     z1[t] = s.z1[t];
   }
+}
+
+// A region to copy next: nq executions (0: nothing), execution q at base + q
+// * qs.
+struct NextStage {
+  const uint8_t* base;
+  uint32_t qs;
+  uint32_t nq;
+};
+
+// Issue the copy of region n (part A, skipping cin blocks in registers).
+// Uniform.
+template <int WIDTH, int B>
+__device__ __forceinline__ void stage_issue(const NextStage& n, uint32_t cin, lds_u8* stage) {
+  if (n.nq) stage_first<WIDTH, B>(n.base, n.qs, n.nq, cin, stage);
+}
+
+// The first region of a task hashing executions g0 .. of a string of N
+// executions at str: a full pass's first region, or the first region of its
+// last, partial pass.
+template <int WIDTH, int B>
+__device__ __forceinline__ NextStage first_region(const uint8_t* str, uint64_t L, uint64_t g0) {
+  using Gm = Geo<B>;
+  constexpr uint64_t XB = Layout<WIDTH, B>::exec_bytes;
+  const uint64_t N = L / XB;
+  if (N - g0 >= (uint64_t)Gm::PASS) return {str + g0 * XB, 8 * (uint32_t)XB, (uint32_t)Gm::G};
+  const uint32_t nv = (uint32_t)(N - g0);
+  return {str + g0 * XB, (uint32_t)XB, nv < (uint32_t)Gm::G ? nv : (uint32_t)Gm::G};
+}
+
+// The task after the current one in its bucket, when its string's metadata
+// has been read (no bucket boundary in between): its first region is copied
+// while the current task's last region is hashed.  The region is worked out
+// only there, so that the metadata loads are not waited for earlier.
+struct TaskNext {
+  bool have;
+  const uint8_t* bytes;
+  uint64_t off, L, tau, texec;
+};
+
+template <int WIDTH, int B>
+__device__ __forceinline__ NextStage task_next_region(const TaskNext& t) {
+  if (!t.have) return {nullptr, 0, 0};
+  return first_region<WIDTH, B>(t.bytes + t.off, t.L, t.tau * t.texec);
 }
 
 template <int WIDTH>
@@ -988,7 +1075,7 @@ __device__ __forceinline__ uint64_t acc_index(uint64_t N, uint32_t j, int l, uin
 // lanes 0 .. LPB-1 (instances 2r, 2r+1 of every tree), into the tree above
 // it.  Called by the whole wave; all control flow is wave-uniform.
 template <int WIDTH, int B, bool ROOTS>
-__device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], uint64_t v1[], uint64_t F[],
+__device__ __forceinline__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], uint64_t v1[], uint64_t F[],
                         uint64_t (*lacc)[Family<WIDTH>::K][B]) {
   constexpr int K = Family<WIDTH>::K;
   using Ly = Layout<WIDTH, B>;
@@ -1097,9 +1184,10 @@ __device__ void fold_up(const Ctx<WIDTH>& c, int l, uint64_t n, uint64_t v0[], u
 // steps, from the lane groups q = 0, 8, 16, ...) or are leftover items of
 // level 1; the executions of the incomplete level-1 node are leftover items
 // of level 0.  Called by the whole wave (nv uniform).
-template <int WIDTH, int B, bool ROOTS>
-__device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
-                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B], lds_u8* stage) {
+template <int WIDTH, int B, bool ROOTS, class Hook = NoHook>
+__device__ __forceinline__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ str, uint64_t p, uint32_t nv,
+                             uint64_t F[], uint64_t (*lacc)[Family<WIDTH>::K][B], lds_u8* stage, bool staged,
+                             const TaskNext& tn, const Hook& first_hook = Hook(), bool call_hook = false) {
   using Ly = Layout<WIDTH, B>;
   using Gm = Geo<B>;
   constexpr int K = Family<WIDTH>::K;
@@ -1123,7 +1211,9 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
     return nv - Gm::G * e < (uint32_t)Gm::G ? nv - Gm::G * e : (uint32_t)Gm::G;
   };
   auto base_of = [&](uint32_t e) { return str + (p + (uint64_t)Gm::G * e) * XB; };
-  stage_first<WIDTH, B>(base_of(0), (uint32_t)XB, nq_of(0), 0, stage);
+  auto region = [&](uint32_t e) -> NextStage { return {base_of(e), (uint32_t)XB, nq_of(e)}; };
+  // (region 0 may have been copied ahead, by the previous task or pass)
+  if (!staged) stage_issue<WIDTH, B>(region(0), 0, stage);
   uint4 xc[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1];  // (no carried blocks here)
   for (uint32_t e = 0; e < steps; ++e) {
     const uint32_t i = Gm::G * e + (uint32_t)q;  // execution within the pass
@@ -1134,9 +1224,14 @@ __device__ void partial_pass(const Ctx<WIDTH>& c, const uint8_t* __restrict__ st
 #pragma unroll
     for (int t = 0; t < K; ++t) t0[t] = t1[t] = 0;
     uint64_t z0[K], z1[K];
-    const bool more = e + 1 < steps;
-    region_ehc<WIDTH, B>(stage, base_of(e), (uint32_t)XB, nq_of(e), 0, 0, more ? base_of(e + 1) : str,
-                         more ? nq_of(e + 1) : 0, 0, xc, uniform_keys(c.ent + Ly::ehc), z0, z1);
+    // the next region: this pass's next step, else the next task's first
+    const NextStage nx = e + 1 < steps ? region(e + 1) : task_next_region<WIDTH, B>(tn);
+    const NextStage cur = region(e);
+    region_ehc<WIDTH, B, false>(stage, cur.base, cur.qs, cur.nq, 0, 0, nx, 0, xc, uniform_keys(c.ent + Ly::ehc), z0,
+                                z1);
+    // (after the region: inside it, the loads' registers would come on top of
+    // the parts')
+    if (call_hook && e == 0) first_hook();
     if (i < nv) {
       if (node_full) {
 #pragma unroll
@@ -1274,6 +1369,79 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, const uint64_t* ltai
   }
 }
 
+// A small string (1 .. kSmallMax executions) per half-wave: every execution
+// is a leftover item of level 0 (no tree node is complete, Eq. (3)), so lane
+// group q of the half hashes execution q (EHC of its instance pair, §3.3,
+// loaded directly) and adds the final NH of the item at level 0, position q
+// (§5.2); the half's lanes add the tail words (Toeplitz keys, §6.1) and the
+// length term, and a half-wave sum gives the output.  `valid` is false for a
+// half without a string.  Called by the whole wave.
+template <int WIDTH, int B>
+__device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* lfin0, const uint64_t* ltail, bool valid,
+                                           uint32_t s, uint64_t L, uint64_t off) {
+  using Ly = Layout<WIDTH, B>;
+  constexpr int K = Family<WIDTH>::K;
+  constexpr uint64_t XB = Ly::exec_bytes;
+  const int l32 = threadIdx.x & 31;
+  const int q = l32 / Geo<B>::LPB, r = l32 % Geo<B>::LPB;
+  const uint8_t* __restrict__ str = a.bytes + off;
+  const uint64_t N = L / XB;
+  uint64_t F[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) F[t] = 0;
+  if (valid && (uint64_t)q < N) {
+    uint64_t z0[K], z1[K];
+    ehc2<WIDTH, B>(str + q * XB + 16 * r, uniform_keys(a.ent + Ly::ehc), z0, z1);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const uint64_t* kf = lfin0 + (t * (kFan - 1) + q) * B;
+      F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
+      F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
+    }
+  }
+  // tail words m0 .. m0 + R - 1 (R <= XB / 8 <= 6 * 32), the last one
+  // zero-padded, loaded to its last byte only
+  const uint64_t tb = N * XB, rem = L - tb;
+  const uint64_t R = (rem + 7) / 8;
+  uint64_t w[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint64_t m = (uint64_t)l32 + 32 * i;
+    w[i] = 0;
+    if (valid && m < R) {
+      const uint8_t* pw = str + tb + 8 * m;
+      if (8 * m + 8 <= rem) {
+        __builtin_memcpy(&w[i], pw, 8);
+      } else {
+        for (uint64_t b = 0; b < rem - 8 * m; ++b) w[i] |= (uint64_t)pw[b] << (8 * b);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint64_t m = (uint64_t)l32 + 32 * i;
+    if (valid && m < R) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w[i], ltail[t + m]);
+    }
+  }
+  if (valid && l32 == 0) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], L, ltail[Ly::len - Ly::tail + t]);
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t)
+#pragma unroll
+    for (int m = 1; m < 32; m <<= 1) F[t] += shfl_xor64(F[t], m);
+  if (valid && l32 < K) {
+    uint64_t v = F[0];
+#pragma unroll
+    for (int t = 1; t < K; ++t)
+      if (l32 == t) v = F[t];
+    __builtin_memcpy(a.out + (uint64_t)s * WIDTH + 8 * l32, &v, 8);
+  }
+}
+
 // Tail-only strings (shorter than one execution: §6.1's tail and the length
 // term, no tree), one string per lane, in chunks of kTinyChunk strings: wave
 // w takes chunks w, w + grid, ...  A tail-only string costs at most a few
@@ -1319,6 +1487,52 @@ __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
     if (s != kNone) tiny_one<WIDTH, B>(a, ltail, s, L, off);
     s = s1;
     s1 = s2;
+    L = L1;
+    off = off1;
+  }
+}
+
+// Small strings (1 .. kSmallMax executions, listed by the planner), one per
+// half-wave: wave w takes the pairs w, w + grid, ... of the list.  The next
+// pair's list entries and metadata are loaded before the current pair is
+// hashed.
+template <int WIDTH, int B>
+__global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
+  using Ly = Layout<WIDTH, B>;
+  constexpr int K = Family<WIDTH>::K;
+  const uint32_t nsmall = uniform(a.ctl[kCtlSmall]);
+  // Toeplitz tail keys, length keys and the final keys of level 0, read at
+  // lane-varying indices, in LDS (one copy per wave)
+  constexpr int NTAIL = (int)(Ly::len + K - Ly::tail);
+  __shared__ uint64_t ltail[NTAIL];
+  __shared__ uint64_t lfin0[K * (kFan - 1) * B];
+  if ((uint64_t)blockIdx.x * 2 >= nsmall) return;  // no pair for this wave
+  for (int i = threadIdx.x; i < NTAIL; i += 64) ltail[i] = a.ent[Ly::tail + i];
+  for (int i = threadIdx.x; i < K * (kFan - 1) * B; i += 64)
+    lfin0[i] = a.ent[Ly::fin + (i / ((kFan - 1) * B)) * kLevels * (kFan - 1) * B + i % ((kFan - 1) * B)];
+  __syncthreads();
+  const uint32_t G = gridDim.x;
+  const int half = threadIdx.x >> 5;
+  // entry of this half in pair k
+  auto meta = [&](uint64_t k, uint32_t& s, uint64_t& L, uint64_t& off) {
+    const uint64_t idx = 2 * k + half;
+    s = idx < nsmall ? a.small_list[idx] : 0xFFFFFFFFu;
+    L = off = 0;
+    if (s != 0xFFFFFFFFu) {
+      L = a.lengths[s];
+      off = a.offsets[s];
+    }
+  };
+  uint64_t k = blockIdx.x;
+  uint32_t s;
+  uint64_t L, off;
+  meta(k, s, L, off);
+  for (; 2 * k < nsmall; k += G) {
+    uint32_t s1;
+    uint64_t L1, off1;
+    meta(k + G, s1, L1, off1);
+    small_half<WIDTH, B>(a, lfin0, ltail, s != 0xFFFFFFFFu, s, L, off);
+    s = s1;
     L = L1;
     off = off1;
   }
@@ -1377,6 +1591,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   bool have_next = false;
   uint32_t pf_s = 0, pf_ts = 0, pf_as = 0;
   uint64_t pf_off = 0, pf_L = 0;
+  // the current task's first region was copied ahead by the previous task
+  bool staged = false;
   for (;;) {
     __builtin_amdgcn_wave_barrier();
     if (fetch) {
@@ -1395,6 +1611,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       task = uniform(a.bucket_lead[k]);
       fetch = false;
       have_next = false;
+      staged = false;
       continue;  // (an empty bucket would fetch again)
     }
     uint32_t s, ts, as;
@@ -1427,6 +1644,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint64_t N = L / XB;
     const uint64_t ntask = N ? (N + texec - 1) / texec : 1;
     const uint8_t* __restrict__ str = a.bytes + off;
+    // the next task of the bucket, whose first region this task copies ahead
+    const TaskNext tn{have_next, a.bytes, pf_off, pf_L, (uint64_t)(task + 1) - pf_ts, texec};
 
     Ctx<WIDTH> c{ent, N, jlev, ntask > 1 ? (uint64_t)as : 0, a.gacc, a.gcnt,
                  ROOTS ? a.roots + (uint64_t)s * (kMaxK * kBlock) : nullptr, ltree, lfin};
@@ -1434,13 +1653,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = 0;
 
-    if (N < Gm::PASS) {
-      // a string of fewer than PASS executions (one task): its tail words
-      // are loaded together with its data, then one partial pass
-      const uint64_t tb = N * XB;
-      const uint64_t rem = L - tb;
-      const uint64_t R = (rem + 7) / 8;  // at most XB / 8 <= 3 * 64 words
-      uint64_t tw[3];
+    // The string's tail words (§6.1: words N XB / 8 .., at most XB / 8 <= 3 *
+    // 64 of them, the last one zero-padded), loaded to its last byte only, in
+    // flight while the last pass's first region is hashed (issued after that
+    // region's bytes have arrived, so that waiting for them never holds up a
+    // region).
+    uint64_t tw[3];
+    auto load_tail = [&]() {
+      const uint64_t tb = N * XB, rem = L - tb, R = (rem + 7) / 8;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
@@ -1454,7 +1674,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           }
         }
       }
-      if (N) partial_pass<WIDTH, B, ROOTS>(c, str, 0, (uint32_t)N, F, lacc, stage);
+    };
+
+    // (at widths 32 and 40, and in the b = 4 family, the registers of the early loads made the
+    // hashing kernel spill: there the tail words are loaded at task start,
+    // or after the passes)
+    constexpr bool kEarlyTail = K <= 3 && B == 8;
+    if (N < Gm::PASS) {
+      // a string of fewer than PASS executions (one task): one partial pass
+      if (N) {
+        if (!kEarlyTail) load_tail();
+        partial_pass<WIDTH, B, ROOTS>(c, str, 0, (uint32_t)N, F, lacc, stage, staged, tn, load_tail, kEarlyTail);
+      } else {
+        stage_issue<WIDTH, B>(task_next_region<WIDTH, B>(tn), 0, stage);
+        load_tail();
+      }
+      const uint64_t R = (L - N * XB + 7) / 8;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
@@ -1472,12 +1707,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       const uint64_t g1 = g0 + texec < N ? g0 + texec : N;
       // the first region of a first full pass is copied ahead
       constexpr uint32_t QS = 8 * (uint32_t)XB;  // lane group stride of a full pass's region
-      if (N - g0 >= (uint64_t)Gm::PASS) stage_first<WIDTH, B>(str + g0 * XB, QS, Gm::G, 0, stage);
+      if (!staged && N - g0 >= (uint64_t)Gm::PASS) stage_first<WIDTH, B>(str + g0 * XB, QS, Gm::G, 0, stage);
       uint4 xc[Parts<WIDTH, B>::LX > 0 ? Parts<WIDTH, B>::LX : 1];  // blocks carried between regions
+      bool pstaged = staged;  // the next pass's first region is copied
+      bool tail_loaded = false;
       for (uint64_t p = g0; p < g1; p += Gm::PASS) {
         if (N - p < Gm::PASS) {
-          // the string's last, partial pass
-          partial_pass<WIDTH, B, ROOTS>(c, str, p, (uint32_t)(N - p), F, lacc, stage);
+          // the string's last, partial pass (in the string's last task: the
+          // tail words are loaded with its first region)
+          tail_loaded = kEarlyTail && tau == ntask - 1;
+          partial_pass<WIDTH, B, ROOTS>(c, str, p, (uint32_t)(N - p), F, lacc, stage, pstaged, tn, load_tail,
+                                        tail_loaded);
           break;
         }
         // full pass: lane group q takes the 8 consecutive executions
@@ -1486,16 +1726,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         uint64_t a0[K], a1[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) a0[t] = a1[t] = 0;
-        // the next pass is a full pass of this task: its first region is
-        // copied during this pass's last step (uniform)
-        const bool next_full = p + Gm::PASS < g1 && N - (p + Gm::PASS) >= (uint64_t)Gm::PASS;
+        // the region after this pass's last step: the next pass's first (a
+        // full pass, or the last, partial one) if this task has one, else
+        // the next task's first (uniform)
+        const bool more = p + Gm::PASS < g1;
         for (int e = 0; e < 8; ++e) {
-          const uint8_t* next = e < 7 ? str + (p + e + 1) * XB : str + (p + Gm::PASS) * XB;
-          const uint32_t nnq = e < 7 || next_full ? (uint32_t)Gm::G : 0;
           const uint32_t cin = e > 0 ? carry_blocks<WIDTH, B>(str, p, e - 1) : 0;
           const uint32_t cout = carry_blocks<WIDTH, B>(str, p, e);
+          const NextStage nx = e < 7 ? NextStage{str + (p + e + 1) * XB, QS, (uint32_t)Gm::G}
+                               : more ? first_region<WIDTH, B>(str, L, p + Gm::PASS)
+                                      : task_next_region<WIDTH, B>(tn);
           uint64_t z0[K], z1[K];
-          region_ehc<WIDTH, B>(stage, str + (p + e) * XB, QS, Gm::G, cin, cout, next, nnq, e < 7 ? cout : 0, xc,
+          region_ehc<WIDTH, B, true>(stage, str + (p + e) * XB, QS, Gm::G, cin, cout, nx, e < 7 ? cout : 0, xc,
                                uniform_keys(ent + Ly::ehc), z0, z1);
           // level 0 of every tree: child e of this lane's level-1 node
           if (e < kFan - 1) {
@@ -1553,23 +1795,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           }
           fold_up<WIDTH, B, ROOTS>(c, 2, (p >> 6) + g, b0, b1, F, lacc);
         }
+        pstaged = true;  // (the next pass's first region was issued in step 7)
       }
 
       if (tau == ntask - 1) {
         // tail (§6.1): words m0 .. m0+R-1, output t keyed by S_tail[t + m]
-        const uint64_t tb = N * XB;
-        const uint64_t rem = L - tb;
-        const uint64_t R = (rem + 7) / 8;
-        for (uint64_t m = lane; m < R; m += 64) {
-          uint64_t w = 0;
-          const uint8_t* pw = str + tb + 8 * m;
-          if (8 * m + 8 <= rem) {
-            __builtin_memcpy(&w, pw, 8);
-          } else {
-            for (uint64_t b = 0; b < rem - 8 * m; ++b) w |= (uint64_t)pw[b] << (8 * b);
-          }
+        if (!tail_loaded) load_tail();
+        const uint64_t R = (L - N * XB + 7) / 8;
 #pragma unroll
-          for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ltail[t + m]);
+        for (int i = 0; i < 3; ++i) {
+          const uint64_t m = (uint64_t)lane + 64 * i;
+          if (m < R) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], tw[i], ltail[t + m]);
+          }
         }
         if (lane == 0) {
 #pragma unroll
@@ -1615,9 +1854,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         }
       }
     }
-    // every lane finishes the task here, before the next one starts
+    // every lane finishes the task here, before the next one starts; the
+    // last region of every task copied the next one's first (when known)
     ++task;
     fetch = (next_entry >> 31) != 0;
+    staged = have_next;
     __builtin_amdgcn_wave_barrier();
   }
 
@@ -1923,6 +2164,12 @@ const void* tiny_kernel_fn(uint32_t width, uint32_t block) {
   return f;
 }
 
+const void* small_kernel_fn(uint32_t width, uint32_t block) {
+  const void* f = nullptr;
+  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&small_kernel<W, Bk>));
+  return f;
+}
+
 uint32_t exec_bytes_of(uint32_t width, uint32_t block) {
   uint32_t x = 0;
   HTH_DISPATCH(width, block, x = Layout<W, Bk>::exec_bytes);
@@ -1943,12 +2190,12 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   const bool scan = nblocks > kPlanScanMin;
   if (nblocks == 1) {
     hipLaunchKernelGGL(plan_single_kernel, dim3(1), dim3(kPlanThreads), 0, stream, p.lengths, p.count, p.exec_bytes,
-                       p.pass_log2, p.direct_lim, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
-                       p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
+                       p.pass_log2, p.direct_lim, p.small_max, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string,
+                       p.task_start, p.acc_start, p.bucket_lead, p.tiny_list, p.small_list, p.ctl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(plan_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                     p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, p.ctl);
+                     p.exec_bytes, p.pass_log2, p.direct_lim, p.small_max, p.block_sums, p.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (scan) {
@@ -1959,24 +2206,25 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   }
   if (scan)
     hipLaunchKernelGGL(plan_fill_kernel<true>, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                       p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks, (const uint64_t*)p.block_pre,
+                       p.exec_bytes, p.pass_log2, p.direct_lim, p.small_max, p.block_sums, nblocks, (const uint64_t*)p.block_pre,
                        p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string, p.task_start,
-                       p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
+                       p.acc_start, p.bucket_lead, p.tiny_list, p.small_list, p.ctl);
   else
     hipLaunchKernelGGL(plan_fill_kernel<false>, dim3(nblocks), dim3(kPlanThreads), 0, stream, p.lengths, p.count,
-                       p.exec_bytes, p.pass_log2, p.direct_lim, p.block_sums, nblocks, (const uint64_t*)nullptr,
+                       p.exec_bytes, p.pass_log2, p.direct_lim, p.small_max, p.block_sums, nblocks, (const uint64_t*)nullptr,
                        p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.task_string, p.task_start,
-                       p.acc_start, p.bucket_lead, p.tiny_list, p.ctl);
+                       p.acc_start, p.bucket_lead, p.tiny_list, p.small_list, p.ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_main(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, uint32_t tiny_grid,
-                       hipStream_t stream) {
-  // the hashing kernel, then the tail-only strings
+                       uint32_t small_grid, hipStream_t stream) {
+  // the hashing kernel, then the tail-only and the small strings
   bool known = false;
   HTH_DISPATCH(width, block, {
     hipLaunchKernelGGL((hash_main_kernel<W, Bk, false>), dim3(grid), dim3(64), 0, stream, a);
     hipLaunchKernelGGL((tiny_kernel<W, Bk>), dim3(tiny_grid), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((small_kernel<W, Bk>), dim3(small_grid), dim3(64), 0, stream, a);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;

@@ -70,6 +70,7 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 Tuning g_tune[4];
 std::map<std::pair<int, int>, uint32_t> g_grid;  // (device, width index + 4 for b = 4) -> persistent grid
 std::map<std::pair<int, int>, uint32_t> g_tiny_grid;  // same keys -> resident tail-only waves
+std::map<std::pair<int, int>, uint32_t> g_small_grid;  // same keys -> resident small-string waves
 
 // Resident waves per compute unit of the tail-only kernel: it is light on
 // registers and latency-bound, so it runs deeper than the hashing kernel.
@@ -92,11 +93,12 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   };
   size_t o_ctl = take(hth::kCtlWords * 4);
   size_t o_bs = take(n.cap_blocks * hth::kBlockSums * 8);
-  size_t o_bp = take(n.cap_blocks * (hth::kPlanSums + 1) * 8);
+  size_t o_bp = take(n.cap_blocks * hth::kPlanPre * 8);
   size_t o_ts = take(n.cap_tasks * 4);
   size_t o_st = take(n.cap_count * 4);
   size_t o_as = take(n.cap_count * 4);
   size_t o_tl = take(n.cap_count * 4);
+  size_t o_sl = take(n.cap_count * 4);
   size_t o_bf = take(((size_t)hth::kMaxBuckets + 2) * 4);
   size_t o_sacc = take(n.cap_count * hth::kMaxK * 8);
   size_t o_sdone = take(n.cap_count * 4);
@@ -120,6 +122,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
   n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
   n.tiny_list = reinterpret_cast<uint32_t*>(b + o_tl);
+  n.small_list = reinterpret_cast<uint32_t*>(b + o_sl);
   n.bucket_lead = reinterpret_cast<uint32_t*>(b + o_bf);
   n.sacc = reinterpret_cast<uint64_t*>(b + o_sacc);
   n.sdone = reinterpret_cast<uint32_t*>(b + o_sdone);
@@ -216,6 +219,34 @@ hth_status tiny_grid_for(uint32_t width, uint32_t block, uint64_t count, uint32_
   return HTH_OK;
 }
 
+// Waves of the small-string kernel for a batch of `count` strings: resident
+// waves, and no more than pairs of strings.
+hth_status small_grid_for(uint32_t width, uint32_t block, uint64_t count, uint32_t* grid) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  uint32_t full = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int key = width_index(width) + (block == 4 ? 4 : 0);
+    auto it = g_small_grid.find({dev, key});
+    if (it != g_small_grid.end()) {
+      full = it->second;
+    } else {
+      int cus = 0, per_cu = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hth::small_kernel_fn(width, block), 64, 0);
+      if (e != hipSuccess) return hip_fail(e, "small-string kernel occupancy query");
+      full = (uint32_t)cus * (uint32_t)(per_cu > 0 ? per_cu : 1);
+      g_small_grid[{dev, key}] = full;
+    }
+  }
+  const uint64_t pairs = (count + 1) / 2;
+  *grid = pairs < full ? (uint32_t)(pairs ? pairs : 1) : full;
+  return HTH_OK;
+}
+
 }  // namespace host
 }  // namespace hth
 
@@ -263,6 +294,8 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   p.exec_bytes = hth::exec_bytes_of(out_width, block);
   p.pass_log2 = hth::pass_log2_of(block);
   p.direct_lim = direct_lim;
+  // (root mode hashes every block in the main kernel: no listed small strings)
+  p.small_max = roots ? 0 : hth::kSmallMax;
   p.block_sums = w.block_sums;
   p.block_pre = w.block_pre;
   p.cap_tasks = w.cap_tasks;
@@ -275,6 +308,7 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   p.acc_start = w.acc_start;
   p.bucket_lead = w.bucket_lead;
   p.tiny_list = w.tiny_list;
+  p.small_list = w.small_list;
   p.ctl = w.ctl;
   hipError_t e = hth::launch_plan(p, stream);
   if (e != hipSuccess) return hip_fail(e, "plan launch");
@@ -294,16 +328,18 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   a.gcnt = w.gcnt;
   a.bucket_lead = w.bucket_lead;
   a.tiny_list = w.tiny_list;
+  a.small_list = w.small_list;
   a.roots = roots;
   a.ctl = w.ctl;
   if (main_start && (e = hipEventRecord(main_start, stream)) != hipSuccess) return hip_fail(e, "event record");
-  uint32_t tiny_grid = 1;
+  uint32_t tiny_grid = 1, small_grid = 1;
   if (!roots) {
     st = tiny_grid_for(out_width, block, count, &tiny_grid);
+    if (st == HTH_OK) st = small_grid_for(out_width, block, count, &small_grid);
     if (st != HTH_OK) return st;
   }
   e = roots ? hth::launch_roots(out_width, block, a, grid, stream)
-            : hth::launch_main(out_width, block, a, grid, tiny_grid, stream);
+            : hth::launch_main(out_width, block, a, grid, tiny_grid, small_grid, stream);
   if (e != hipSuccess) return hip_fail(e, "main launch");
   if (main_stop && (e = hipEventRecord(main_stop, stream)) != hipSuccess) return hip_fail(e, "event record");
   return HTH_OK;
@@ -459,6 +495,7 @@ hth_status hth_batch_graph_create(const hth_seed* seed, const uint8_t* bytes, co
   uint32_t grid = 0;
   st = grid_for(out_width, seed->block, &grid);  // fills the caches outside the capture
   if (st == HTH_OK) st = tiny_grid_for(out_width, seed->block, count, &grid);
+  if (st == HTH_OK) st = small_grid_for(out_width, seed->block, count, &grid);
   if (st != HTH_OK) return st;
   hth_batch_graph* g = new (std::nothrow) hth_batch_graph;
   if (!g) return fail(HTH_E_OOM, "hth_batch_graph_create: host allocation");

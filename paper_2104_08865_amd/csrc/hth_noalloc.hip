@@ -29,11 +29,12 @@ constexpr size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t kOffCtl = 0;
 constexpr size_t kOffBs = kOffCtl + up256(hth::kCtlWords * 4);
 constexpr size_t kOffBp = kOffBs + up256(kNaBlocks * hth::kBlockSums * 8);
-constexpr size_t kOffTs = kOffBp + up256(kNaBlocks * (hth::kPlanSums + 1) * 8);
+constexpr size_t kOffTs = kOffBp + up256(kNaBlocks * hth::kPlanPre * 8);
 constexpr size_t kOffSt = kOffTs + up256(kNaTasks * 4);
 constexpr size_t kOffAs = kOffSt + up256(kNaCount * 4);
 constexpr size_t kOffTl = kOffAs + up256(kNaCount * 4);
-constexpr size_t kOffBl = kOffTl + up256(kNaCount * 4);
+constexpr size_t kOffSl = kOffTl + up256(kNaCount * 4);
+constexpr size_t kOffBl = kOffSl + up256(kNaCount * 4);
 constexpr size_t kOffSacc = kOffBl + up256(((size_t)hth::kMaxBuckets + 2) * 4);
 constexpr size_t kOffSdone = kOffSacc + up256(kNaCount * hth::kMaxK * 8);
 constexpr size_t kOffGacc = kOffSdone + up256(kNaCount * 4);
@@ -91,6 +92,7 @@ Workspace na_workspace(uint8_t* b) {
   w.task_start = reinterpret_cast<uint32_t*>(b + kOffSt);
   w.acc_start = reinterpret_cast<uint32_t*>(b + kOffAs);
   w.tiny_list = reinterpret_cast<uint32_t*>(b + kOffTl);
+  w.small_list = reinterpret_cast<uint32_t*>(b + kOffSl);
   w.bucket_lead = reinterpret_cast<uint32_t*>(b + kOffBl);
   w.sacc = reinterpret_cast<uint64_t*>(b + kOffSacc);
   w.sdone = reinterpret_cast<uint32_t*>(b + kOffSdone);
