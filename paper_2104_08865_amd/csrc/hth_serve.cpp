@@ -6,15 +6,19 @@
 //
 // Data path of one request:
 //   submit:  bytes copied into a pinned host ring (FIFO allocation);
-//   worker:  admitted when the device ring (the memory budget) has room,
+//   slot:    admitted when the device ring (the memory budget) has room,
 //            packed with the other admitted requests into a batch, copied
-//            host ring -> device ring on the batch's stream, hashed (one
+//            host ring -> device ring on the slot's stream, hashed (one
 //            launch per output width present), results copied back to a
 //            pinned buffer;
 //   retire:  when the batch's event completes, results move to the ticket
-//            table, both ring regions are released and latencies recorded.
-// Batches go to `slots` streams round robin, so the copies of one batch
-// overlap the hashing of another.
+//            table and latencies are recorded; ring regions are released in
+//            admission order (both rings are FIFO), once every earlier batch
+//            has completed too.
+// Each of the `slots` slots has a stream and a thread of its own, which
+// admits a new batch as soon as its previous one has retired: the host work
+// of building and enqueueing batches (a dozen HIP calls each) runs on
+// several threads, and the copies of one batch overlap the hashing of others.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -102,8 +106,14 @@ struct Slot {
   uint8_t* d_out = nullptr;
   std::vector<Request> reqs;
   uint64_t out_at[kWidths] = {};  // byte offset of each width group in the results
-  uint64_t host_end = 0, dev_end = 0;
-  bool busy = false;
+  uint64_t seq = 0;               // admission number of the slot's batch
+};
+
+// A batch between its admission and the release of its ring regions.
+struct Inflight {
+  uint64_t seq;
+  uint64_t host_end, dev_end;
+  bool done;
 };
 
 enum : uint8_t { kFree = 0, kPending = 1, kReady = 2 };
@@ -126,21 +136,20 @@ struct hth_server {
   uint8_t* d_ring = nullptr;
   std::vector<Slot> slots;
 
-  // host ring and pending queue (queue order = host ring order); a
-  // request's bytes are copied outside the lock, so the worker admits a
-  // request only once its `copied` flag is set
+  // host ring, device ring, pending queue (queue order = host ring order)
+  // and the batches in flight (admission order), all under q_mu; a
+  // request's bytes are copied outside the lock, so a slot admits a request
+  // only once its `copied` flag is set
   std::mutex q_mu;
   std::condition_variable q_cv;
   Ring host;
+  Ring dev;
   std::deque<Request> pending;
   uint64_t next_ticket = 1;
   std::unique_ptr<std::atomic<uint8_t>[]> copied;  // per ticket slot
-  std::atomic<uint64_t> ready_hint{0};            // submits since the worker last looked
-  std::atomic<bool> worker_idle{false};
-
-  Ring dev;  // worker only
-  uint32_t next_slot = 0;
-  std::deque<uint32_t> inflight;  // slot indices in launch order
+  std::atomic<int> idle_slots{0};                 // slot threads looking for requests
+  uint64_t next_seq = 0;
+  std::deque<Inflight> inflight;
 
   // tickets
   std::mutex r_mu;
@@ -158,8 +167,9 @@ struct hth_server {
   std::atomic<bool> stop{false};
   std::atomic<bool> paused{false};
   std::atomic<int> failed{0};
+  std::atomic<bool> fail_claimed{false};
   std::string fail_msg;  // written once, before `failed` is set
-  std::thread worker;
+  std::vector<std::thread> workers;  // one per slot
 };
 
 namespace {
@@ -169,7 +179,7 @@ hth_status server_error(hth_server* s) {
 }
 
 void set_failed(hth_server* s, hipError_t e, const char* what) {
-  if (s->failed.load()) return;
+  if (s->fail_claimed.exchange(true)) return;  // the first error is the one reported
   s->fail_msg = std::string(what) + ": " + hipGetErrorString(e);
   s->failed.store(1);
   s->q_cv.notify_all();
@@ -177,38 +187,39 @@ void set_failed(hth_server* s, hipError_t e, const char* what) {
   s->r_cv.notify_all();
 }
 
-// Moves admitted requests from the queue into slot `si` and enqueues the
-// batch.  Returns false when nothing was admitted.
-bool launch_batch(hth_server* s, uint32_t si) {
-  Slot& sl = s->slots[si];
+// Admits requests from the head of the queue into slot `sl` (q_mu held):
+// only requests whose bytes are copied, while the device ring has room and
+// the batch limits allow.  Returns false when nothing was admitted.
+bool admit_locked(hth_server* s, Slot& sl) {
   sl.reqs.clear();
   uint64_t bytes = 0;
-  {
-    std::lock_guard<std::mutex> lk(s->q_mu);
-    while (!s->pending.empty() && sl.reqs.size() < s->cfg.max_batch_requests) {
-      Request& r = s->pending.front();
-      if (!s->copied[r.ticket & s->mask].load(std::memory_order_acquire)) break;  // bytes still being copied
-      if (!sl.reqs.empty() && bytes + r.len > s->cfg.max_batch_bytes) break;
-      uint64_t pos = 0;
-      if (!s->dev.alloc(pad(r.len), &pos)) {
-        // device budget exhausted: the request waits for a batch to retire
-        if (!r.deferred) {
-          r.deferred = true;
-          std::lock_guard<std::mutex> rl(s->r_mu);
-          ++s->n_deferred;
-        }
-        break;
+  while (!s->pending.empty() && sl.reqs.size() < s->cfg.max_batch_requests) {
+    Request& r = s->pending.front();
+    if (!s->copied[r.ticket & s->mask].load()) break;  // bytes still being copied
+    if (!sl.reqs.empty() && bytes + r.len > s->cfg.max_batch_bytes) break;
+    uint64_t pos = 0;
+    if (!s->dev.alloc(pad(r.len), &pos)) {
+      // device budget exhausted: the request waits for a batch to retire
+      if (!r.deferred) {
+        r.deferred = true;
+        std::lock_guard<std::mutex> rl(s->r_mu);
+        ++s->n_deferred;
       }
-      r.dev_pos = pos;
-      bytes += r.len;
-      sl.reqs.push_back(r);
-      s->pending.pop_front();
+      break;
     }
+    r.dev_pos = pos;
+    bytes += r.len;
+    sl.reqs.push_back(r);
+    s->pending.pop_front();
   }
   if (sl.reqs.empty()) return false;
-  sl.host_end = sl.reqs.back().host_pos + pad(sl.reqs.back().len);
-  sl.dev_end = s->dev.head;
+  sl.seq = s->next_seq++;
+  s->inflight.push_back(Inflight{sl.seq, sl.reqs.back().host_pos + pad(sl.reqs.back().len), s->dev.head, false});
+  return true;
+}
 
+// Enqueues the admitted batch of slot `sl` on its stream (no lock held).
+bool launch_batch(hth_server* s, Slot& sl) {
   // group by width, in submission order inside each group
   uint64_t n[kWidths] = {};
   for (const Request& r : sl.reqs) ++n[widx(r.width)];
@@ -267,21 +278,12 @@ bool launch_batch(hth_server* s, uint32_t si) {
     set_failed(s, e, "batch download");
     return false;
   }
-  sl.busy = true;
-  s->inflight.push_back(si);
   return true;
 }
 
-// Publishes the results of the oldest batch if its event completed.
-bool retire_one(hth_server* s) {
-  if (s->inflight.empty()) return false;
-  Slot& sl = s->slots[s->inflight.front()];
-  hipError_t e = hipEventQuery(sl.done);
-  if (e == hipErrorNotReady) return false;
-  if (e != hipSuccess) {
-    set_failed(s, e, "batch completion");
-    return false;
-  }
+// Publishes the results of slot `sl`'s completed batch, then releases the
+// ring regions of the completed batches at the head of the admission order.
+void retire(hth_server* s, Slot& sl) {
   const Clock::time_point now = Clock::now();
   uint64_t fillw[kWidths] = {}, bytes = 0;
   {
@@ -302,57 +304,57 @@ bool retire_one(hth_server* s) {
     s->t_last = now;
     s->r_cv.notify_all();
   }
-  s->dev.release(sl.dev_end);
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
-    s->host.release(sl.host_end);
+    for (Inflight& f : s->inflight)
+      if (f.seq == sl.seq) f.done = true;
+    while (!s->inflight.empty() && s->inflight.front().done) {
+      s->host.release(s->inflight.front().host_end);
+      s->dev.release(s->inflight.front().dev_end);
+      s->inflight.pop_front();
+    }
   }
-  s->q_cv.notify_all();  // submitters waiting for host ring space
-  sl.busy = false;
-  s->inflight.pop_front();
-  return true;
+  s->q_cv.notify_all();  // slots waiting for device ring space
+  sl.reqs.clear();
 }
 
-void worker_main(hth_server* s) {
+// The thread of slot `si`: admit a batch, enqueue it, wait for it, retire
+// it, until the server stops or fails.
+void worker_main(hth_server* s, uint32_t si) {
   if (hipSetDevice(s->device) != hipSuccess) {
-    set_failed(s, hipErrorInvalidDevice, "worker hipSetDevice");
+    set_failed(s, hipErrorInvalidDevice, "slot thread hipSetDevice");
     return;
   }
-  while (!s->stop.load() && !s->failed.load()) {
-    bool progress = false;
-    while (retire_one(s)) progress = true;
-    if (s->failed.load()) break;
-    Slot& next = s->slots[s->next_slot];
-    if (!next.busy && !s->paused.load() && s->ready_hint.load(std::memory_order_acquire)) {
-      s->ready_hint.store(0, std::memory_order_relaxed);  // launch_batch looks at the whole queue
-      if (launch_batch(s, s->next_slot)) {
-        s->next_slot = (s->next_slot + 1) % (uint32_t)s->slots.size();
-        progress = true;
-      }
-      bool more = false;
-      {
-        std::lock_guard<std::mutex> lk(s->q_mu);
-        more = !s->pending.empty();
-      }
-      if (more) {
-        s->ready_hint.fetch_add(1, std::memory_order_relaxed);  // look again next round
-        if (!progress) std::this_thread::yield();  // the head request's bytes are still being copied
-      }
-    }
-    if (progress) continue;
-    if (s->inflight.empty()) {
+  Slot& sl = s->slots[si];
+  for (;;) {
+    bool got = false;
+    {
       std::unique_lock<std::mutex> lk(s->q_mu);
-      s->worker_idle.store(true);
-      s->q_cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
-        return s->stop.load() || (s->ready_hint.load() && !s->paused.load());
-      });
-      s->worker_idle.store(false);
-    } else {
-      std::this_thread::yield();  // a batch is in flight: poll its event
+      // counted idle before looking at the queue: a submit that the look
+      // misses sees the count and wakes a slot (both are sequentially
+      // consistent atomics)
+      s->idle_slots.fetch_add(1);
+      for (;;) {
+        if (s->stop.load() || s->failed.load()) break;
+        if (!s->paused.load() && admit_locked(s, sl)) {
+          got = true;
+          break;
+        }
+        s->q_cv.wait_for(lk, std::chrono::milliseconds(50));
+      }
+      s->idle_slots.fetch_sub(1);
     }
+    if (!got || !launch_batch(s, sl)) return;
+    // poll the batch's event: a blocking wait adds a wake-up to every
+    // request's latency
+    hipError_t e;
+    while ((e = hipEventQuery(sl.done)) == hipErrorNotReady) std::this_thread::yield();
+    if (e != hipSuccess) {
+      set_failed(s, e, "batch completion");
+      return;
+    }
+    retire(s, sl);
   }
-  // drain what is in flight so that buffers are idle before destruction
-  for (uint32_t si : s->inflight) (void)hipEventSynchronize(s->slots[si].done);
 }
 
 void free_server(hth_server* s) {
@@ -369,6 +371,28 @@ void free_server(hth_server* s) {
   if (s->h_ring) (void)hipHostFree(s->h_ring);
   if (s->d_ring) (void)hipFree(s->d_ring);
   delete s;
+}
+
+// Writes every page of a pinned host buffer once.  The pages are resident
+// from the allocation on, but the process's page table maps them on first
+// touch, one fault per page: left to the submitters, those faults cost more
+// than the copies themselves (a 30 KB request touches 8 pages) and
+// serialise threads on the address space lock.
+void prefault(uint8_t* p, uint64_t n) {
+  constexpr uint64_t kPage = 4096;
+  const uint32_t nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const uint64_t per = (n / kPage + nt - 1) / nt * kPage;
+  auto touch = [&](uint64_t lo) {
+    for (uint64_t o = lo; o < std::min(n, lo + per); o += kPage) p[o] = 0;
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(touch, (uint64_t)t * per);
+  } catch (...) {
+    for (uint32_t t = (uint32_t)pool.size() + 1; t < nt; ++t) touch((uint64_t)t * per);
+  }
+  touch(0);
+  for (auto& th : pool) th.join();
 }
 
 hth_status take(hth_server* s, uint64_t ticket, uint8_t* out, bool block) {
@@ -448,6 +472,7 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
   const char* what = "";
   e = hipHostMalloc((void**)&s->h_ring, c.host_stage_bytes, hipHostMallocDefault);
   what = "staging ring";
+  if (e == hipSuccess) prefault(s->h_ring, c.host_stage_bytes);
   if (e == hipSuccess) {
     e = hipMalloc((void**)&s->d_ring, c.max_device_bytes);
     what = "device ring";
@@ -475,10 +500,16 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
     return fail(st, "hth_serve_create: %s", msg.c_str());
   }
   try {
-    s->worker = std::thread(worker_main, s);
+    for (uint32_t i = 0; i < c.slots; ++i) s->workers.emplace_back(worker_main, s, i);
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(s->q_mu);
+      s->stop.store(true);
+    }
+    s->q_cv.notify_all();
+    for (auto& t : s->workers) t.join();
     free_server(s);
-    return fail(HTH_E_OOM, "hth_serve_create: worker thread");
+    return fail(HTH_E_OOM, "hth_serve_create: slot thread");
   }
   *out = s;
   return HTH_OK;
@@ -528,11 +559,11 @@ hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len,
     s->pending.push_back(Request{t, pos, 0, len, out_width, false, t0});
   }
   if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
-  s->copied[t & s->mask].store(1, std::memory_order_release);
-  s->ready_hint.fetch_add(1);  // sequentially consistent with the worker's idle flag
-  if (s->worker_idle.load()) {
-    std::lock_guard<std::mutex> lk(s->q_mu);  // pairs with the worker's predicate check
-    s->q_cv.notify_all();
+  s->copied[t & s->mask].store(1);
+  if (s->idle_slots.load()) {
+    // the lock orders the notify after an idle slot's look at the queue
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->q_cv.notify_one();
   }
   *ticket = t;
   return HTH_OK;
@@ -608,7 +639,6 @@ hth_status hth_serve_pause(hth_server* s, int32_t paused) {
   {
     std::lock_guard<std::mutex> lk(s->q_mu);
     s->paused.store(paused != 0);
-    if (!paused) s->ready_hint.fetch_add(1);
   }
   s->q_cv.notify_all();
   return HTH_OK;
@@ -665,9 +695,13 @@ hth_status hth_serve_reset_stats(hth_server* s) {
 
 hth_status hth_serve_destroy(hth_server* s) {
   if (!s) return HTH_OK;
-  s->stop.store(true);
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->stop.store(true);
+  }
   s->q_cv.notify_all();
-  if (s->worker.joinable()) s->worker.join();
+  for (auto& t : s->workers)
+    if (t.joinable()) t.join();
   const bool was_failed = s->failed.load() != 0;
   std::string msg = s->fail_msg;
   free_server(s);
