@@ -104,7 +104,10 @@ hth_status hth_seed_free(hth_seed *seed);
 /* Batched hashing.                                                          */
 /* ------------------------------------------------------------------------ */
 
-/* Hash `count` byte strings with one family member H(seed, .).
+/* Hash `count` byte strings with one family member H(seed, .): the seeded
+ * hash family of §1, almost-universal among strings of equal length (§2),
+ * computed as EHC per block (§3.3, §4, §5.1), the tree of Eq. (3) with the
+ * final NH (§5.2), the Toeplitz tail (§6.1) and a length term.
  *
  *   bytes    device pointer; string i is bytes[offsets[i], offsets[i] +
  *            lengths[i]).  No alignment is required; strings may overlap.
@@ -117,8 +120,9 @@ hth_status hth_seed_free(hth_seed *seed);
  *
  * out[i] depends only on the seed and string i, never on the rest of the
  * batch.  The call enqueues a short planning step, one persistent hashing
- * kernel and a small kernel for the strings shorter than one EHC execution
- * (tail only) on `stream` and returns.  Scratch memory comes from a per-stream workspace
+ * kernel, a small kernel for the strings shorter than one EHC execution
+ * (tail only) and one for the strings of 1 .. 7 executions on `stream` and
+ * returns.  Scratch memory comes from a per-stream workspace
  * that the library grows on the host as `count` grows (hth_reserve
  * pre-allocates it, e.g. before stream capture: a call inside a capture never
  * allocates and fails with HTH_E_INVALID if the workspace is too small).
@@ -178,8 +182,10 @@ hth_status hth_tab_expand(uint64_t user_seed, uint32_t inner_width, uint64_t *wo
              owned by the caller (valid until `stream` reaches this work);
      out     device pointer to count uint64_t, 8-byte aligned.
    Enqueues the planner and hashing kernels of hth_hash_batch for the strings
-   longer than inner_width bytes (their values go to the stream's workspace),
-   then one tabulation kernel for every string, on `stream`.  Same workspace
+   longer than 64 bytes (their values go to the stream's workspace), then one
+   tabulation kernel for every string, on `stream`; that kernel computes the
+   HalftimeHash value of a string of inner_width + 1 .. 64 bytes itself (the
+   tail and length terms of a string shorter than one execution).  Same workspace
    rules as hth_hash_batch.  Errors: HTH_E_INVALID (as hth_hash_batch, null
    or misaligned tables/out with count > 0), HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_hash_batch64(const hth_seed *seed, const uint64_t *tables, const uint8_t *bytes,
@@ -232,7 +238,7 @@ hth_status hth_batch_graph_free(hth_batch_graph *graph);
    different streams, or different host threads without ordering) race and
    give wrong values.  Order them on one stream. */
 #define HTH_NOALLOC_MAX_COUNT 65536
-#define HTH_NOALLOC_SCRATCH_BYTES 7386112
+#define HTH_NOALLOC_SCRATCH_BYTES 7406592
 hth_status hth_hash_batch_noalloc(const hth_seed *seed, const uint8_t *bytes, const uint64_t *offsets,
                                   const uint64_t *lengths, uint64_t count, uint8_t *out, uint32_t out_width,
                                   hipStream_t stream);

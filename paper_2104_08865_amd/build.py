@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhth.so")
-SOURCES = ["hth_kernels.hip", "hth_compose.hip", "hth_lib.cpp", "hth_serve.cpp", "hth_stream.cpp", "hth_compose.cpp", "hth_noalloc.hip"]
+SOURCES = ["hth_kernels.hip", "hth_lib.cpp", "hth_serve.cpp", "hth_stream.cpp", "hth_compose.cpp", "hth_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

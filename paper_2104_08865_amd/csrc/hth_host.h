@@ -28,6 +28,7 @@ struct Workspace {
   uint32_t* ctl = nullptr;
   uint64_t* block_sums = nullptr;
   uint64_t* block_pre = nullptr;
+  uint64_t* group_sums = nullptr;
   uint32_t* task_string = nullptr;
   uint32_t* task_start = nullptr;
   uint32_t* acc_start = nullptr;

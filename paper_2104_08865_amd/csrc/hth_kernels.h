@@ -35,9 +35,13 @@ constexpr int kPlanPre = kPlanSums + 2;
 // task either: listed apart, one per half-wave of the small-string kernel.
 constexpr int kTinyChunk = 64;
 constexpr uint32_t kSmallMax = 7;
-// Plans of more planner blocks than this get the scan kernel between their
+// Plans of more planner blocks than this get two scan kernels between their
 // two steps (linear in the block count); smaller ones sum in the fill step.
+// The scan cuts the blocks into at most kScanGroups runs of at least
+// kScanGroupMin blocks, one workgroup each.
 constexpr uint32_t kPlanScanMin = 256;
+constexpr uint32_t kScanGroups = 128;
+constexpr uint32_t kScanGroupMin = 64;
 
 // Control words of one launch (device memory, written by the planner).
 enum {
@@ -62,6 +66,7 @@ struct PlanArgs {
   uint32_t small_max;     // strings of 1 .. small_max executions are listed as small (0: none)
   uint64_t* block_sums;  // [kBlockSums][nblocks] (column-major)
   uint64_t* block_pre;   // [kPlanPre][nblocks]: per-block prefixes (large plans)
+  uint64_t* group_sums;  // [kBlockSums][kScanGroups]: per-run sums (large plans)
   uint64_t cap_tasks, cap_accs;
   uint32_t min_j, max_j;   // task level range the planner may choose from
   uint64_t target_tasks;   // prefer the coarsest level with at least this many tasks
@@ -112,18 +117,24 @@ const void* tiny_kernel_fn(uint32_t width, uint32_t block);
 const void* small_kernel_fn(uint32_t width, uint32_t block);
 
 // Composition with simple tabulation: one string per thread; the string's
-// key is its own bytes (lengths <= width) or its HalftimeHash value in h.
+// key is its own bytes (lengths <= width) or its HalftimeHash value: computed
+// by the tabulation kernel itself for strings of at most kTabInline bytes
+// (tail-only strings of at most 8 words), read from h for longer ones (the
+// planner's direct_lim is kTabInline + 1, so the hashing kernels write h for
+// exactly those).
+constexpr uint32_t kTabInline = 64;
 struct TabArgs {
   const uint8_t* bytes;
   const uint64_t* offsets;
   const uint64_t* lengths;
   uint64_t count;
-  const uint8_t* h;        // [count][width]: values of the strings longer than width bytes
+  const uint8_t* h;        // [count][width]: values of the strings longer than kTabInline bytes
   const uint64_t* tables;  // [(width + 1) * 256]
+  const uint64_t* ent;     // this width's entropy block (tail and length keys)
   uint64_t* out;           // [count]
 };
-hipError_t launch_tab(uint32_t width, const TabArgs& a, uint32_t grid, hipStream_t stream);
-const void* tab_kernel_fn(uint32_t width);
+hipError_t launch_tab(uint32_t width, uint32_t block, const TabArgs& a, uint32_t grid, hipStream_t stream);
+const void* tab_kernel_fn(uint32_t width, uint32_t block);
 // Threads of one tabulation workgroup.
 constexpr int kTabThreads = 1024;
 

@@ -3,18 +3,23 @@
 // One launch hashes a whole batch of strings.  Work is cut into tasks: a task
 // is an aligned range of T = 128 * 8^j full EHC executions of one string (the
 // last task of a string also takes its tail, its length term and any partial
-// range).  A planner (two small kernels, or one for small batches, plus a
-// scan kernel for large ones) cuts the task list into buckets of about equal
+// range).  A planner (two small kernels, or one for small batches, plus two
+// scan kernels for large ones) cuts the task list into buckets of about equal
 // work; a persistent grid of single-wave workgroups pulls whole buckets from
 // a device counter.  Strings shorter than one execution have no task: a
-// separate tail-only kernel hashes them, one string per lane.
+// separate tail-only kernel hashes them, one string per lane; strings of 1 ..
+// kSmallMax executions have none either: a small-string kernel hashes them,
+// one per half-wave.  The composed 64-bit hash's tabulation kernel is here
+// too (it computes the value of short tail-only strings itself).
 //
 // Inside a task a wave works in passes of 128 executions.  Lane l = 4q + r
 // (q = 0..15, r = 0..3) owns instances 2r and 2r+1 (the two 64-bit words of a
-// 16-byte load inside each 64-byte block, paper §2: instance j = word j of
-// every block) of the 8 consecutive executions p + 8q .. p + 8q + 7.  For each
-// execution it loads the d*w blocks with 16-byte loads, runs Encode, Hash and
-// Combine (§3.3, §4, §5.1) in registers, and feeds the k outputs into the
+// 16-byte piece of each 64-byte block, paper §2: instance j = word j of
+// every block) of the 8 consecutive executions p + 8q .. p + 8q + 7.  The
+// executions reach the wave through LDS (copied from HBM by direct-to-LDS
+// loads, one region of 16 executions at a time, while the previous region is
+// hashed); for each execution a lane reads its blocks' pieces, runs Encode,
+// Hash and Combine (§3.3, §4, §5.1) in registers, and feeds the k outputs into the
 // first tree level: 8 consecutive executions of a lane form one level-1 node
 // of every tree, so levels 0 and 1 need no data exchange.  Level 2 (64
 // executions) is a 3-step butterfly over lanes q, q^1, q^2, q^4 of each half
@@ -276,8 +281,8 @@ constexpr int kPlanPer = 4;
 constexpr int kPlanBlock = kPlanThreads * kPlanPer;
 
 constexpr int kPlanWaves = kPlanThreads / 64;
-// The scan step of large plans runs in one workgroup of this many threads.
-constexpr int kScanThreads = 1024;
+// Threads of a workgroup of the scan kernels of large plans.
+constexpr int kScanThreads = 256;
 
 // Sums of n values over a workgroup of NT threads, returned to every
 // thread, with one pair of barriers for all of them.
@@ -358,6 +363,19 @@ __device__ void block_exclusive_n(uint64_t (&v)[NV], uint64_t (*lds)[NV], uint64
   }
 }
 
+// A thread's kPlanPer consecutive lengths from `base` (zero past count): in
+// 16-byte loads when all are inside, so that a load instruction reads 1 KiB
+// of consecutive lengths.
+__device__ __forceinline__ void load_lengths(const uint64_t* __restrict__ lengths, uint64_t count, uint64_t base,
+                                             uint64_t (&L)[kPlanPer]) {
+  if (base + kPlanPer <= count) {
+    __builtin_memcpy(L, lengths + base, 8 * kPlanPer);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) L[i] = base + i < count ? lengths[base + i] : 0;
+  }
+}
+
 // Planning step 1 for workgroup `blk`: per candidate task size, the tasks,
 // accumulators and work of its kPlanBlock strings.
 // `v` receives the workgroup's sums (every thread) and `L` this thread's
@@ -371,11 +389,11 @@ __device__ void plan_count_body(uint32_t blk, const uint64_t* __restrict__ lengt
   // the fill kernel appends bucket leaders to this counter
   if (blk == 0 && threadIdx.x == 0) ctl[kCtlBuckets] = 0;
   const uint64_t base = (uint64_t)blk * kPlanBlock + threadIdx.x * kPlanPer;
+  load_lengths(lengths, count, base, L);
   uint64_t N[kPlanPer];
   bool any = false;
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
-    L[i] = base + i < count ? lengths[base + i] : 0;
     N[i] = task_execs(L[i], exec_bytes, small_max);
     any |= N[i] != 0;
   }
@@ -512,6 +530,12 @@ __device__ void plan_fill_body(
     jsel = ctl[kCtlError] ? -1 : (int)ctl[kCtlLevel];
     bucket = (uint64_t)ctl[kCtlBucketLo] | (uint64_t)ctl[kCtlBucketHi] << 32;
     if (jsel < 0) return;  // uniform over the grid
+    // a block with no task and no listed string writes nothing (batches of
+    // keys short enough for the composed hash's direct path): its lengths
+    // are not read again
+    if (!(block_sums[(uint64_t)(jsel * kPlanSums) * nblocks + blk] | block_sums[(uint64_t)kSumTiny * nblocks + blk] |
+          block_sums[(uint64_t)kSumSmall * nblocks + blk]))
+      return;  // uniform over the workgroup
 #pragma unroll
     for (int k = 0; k < kPlanPre; ++k) pre[k] = block_pre[(uint64_t)k * nblocks + blk];
   } else {
@@ -541,6 +565,13 @@ __device__ void plan_fill_body(
   const uint64_t small_base = pre[4];
 
   const uint64_t base = (uint64_t)blk * kPlanBlock + tid * kPlanPer;
+  uint64_t Ls[kPlanPer];
+  if constexpr (MODE == kFillSingle) {
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) Ls[i] = len_in[i];
+  } else {
+    load_lengths(lengths, count, base, Ls);
+  }
   uint64_t tk[kPlanPer], ac[kPlanPer], wk[kPlanPer];
   uint64_t st = 0, sa = 0, sw = 0, sy = 0, sm = 0;
   bool tiny[kPlanPer], small[kPlanPer];
@@ -549,7 +580,7 @@ __device__ void plan_fill_body(
     tk[i] = ac[i] = wk[i] = 0;
     tiny[i] = small[i] = false;
     if (base + i < count) {
-      const uint64_t L = MODE == kFillSingle ? len_in[i] : lengths[base + i];
+      const uint64_t L = Ls[i];
       slen[tid * kPlanPer + i] = L;
       plan_counts(task_execs(L, exec_bytes, small_max), jsel, pass_log2, tk[i], ac[i]);
       wk[i] = tk[i] ? L + kTaskOverheadBytes * tk[i] : 0;
@@ -654,73 +685,88 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(const uint64_t
   plan_count_body(blockIdx.x, lengths, count, exec_bytes, pass_log2, direct_lim, small_max, block_sums, ctl, v, L);
 }
 
-// Large plans, between the two steps: totals, the task level and bucket
-// size (control words), and every block's exclusive prefix of tasks,
-// accumulators, work and tail-only strings at that level, in one workgroup
-// (linear in the block count).  Wave w owns a contiguous run of blocks, so
-// its loads read consecutive words of one column (a single workgroup is
-// bound by its cache-line requests and round trips, not by bytes); the run's
-// prefixes are wave scans, offset by the earlier waves' totals of the first
-// pass.
-__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(
-    const uint64_t* __restrict__ block_sums, uint32_t nblocks, uint64_t cap_tasks, uint64_t cap_accs,
-    uint32_t min_j, uint32_t max_j, uint64_t target_tasks, uint64_t* __restrict__ block_pre,
-    uint32_t* __restrict__ ctl) {
-  constexpr int NP = kPlanPre, NW = kScanThreads / 64;
-  __shared__ uint64_t ldsn[NW][kBlockSums];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t per = (nblocks + NW - 1) / NW;
-  const uint32_t r0 = w * per < nblocks ? w * per : nblocks;
-  const uint32_t r1 = r0 + per < nblocks ? r0 + per : nblocks;
-  // totals of every column; ldsn keeps each wave's totals
+// Large plans, between the two steps, in two launches of one workgroup per
+// run of blocks (at most kScanGroups runs of at least kScanGroupMin blocks):
+// the first sums each run's step-1 results (group_sums, column-major
+// [kBlockSums][ngroups]); in the second every workgroup sums the runs (the
+// totals, the same in each), chooses the task level and bucket size
+// (workgroup 0 writes the control words), adds the runs before its own for
+// its exclusive prefix, and writes the prefixes of tasks, accumulators,
+// work, tail-only and small strings of its run's blocks, kScanThreads
+// blocks per round.  (One workgroup over every block took 72 us for 16,384
+// blocks: a single workgroup is bound by its round trips, not by bytes.)
+__device__ __forceinline__ void scan_run(uint32_t nblocks, uint32_t ngroups, uint32_t g, uint32_t& r0, uint32_t& r1) {
+  const uint32_t per = (nblocks + ngroups - 1) / ngroups;
+  r0 = g * per < nblocks ? g * per : nblocks;
+  r1 = r0 + per < nblocks ? r0 + per : nblocks;
+}
+
+__global__ __launch_bounds__(kScanThreads) void plan_group_kernel(const uint64_t* __restrict__ block_sums,
+                                                                  uint32_t nblocks,
+                                                                  uint64_t* __restrict__ group_sums) {
+  __shared__ uint64_t ldsn[kScanThreads / 64][kBlockSums];
+  uint32_t r0, r1;
+  scan_run(nblocks, gridDim.x, blockIdx.x, r0, r1);
   uint64_t tot[kBlockSums];
 #pragma unroll
   for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
-#pragma unroll 2  // two rows of loads in flight, without spills
-  for (uint32_t b = r0 + lane; b < r1; b += 64)
+  for (uint32_t b = r0 + threadIdx.x; b < r1; b += kScanThreads)
 #pragma unroll
     for (int k = 0; k < kBlockSums; ++k) tot[k] += block_sums[(uint64_t)k * nblocks + b];
   block_sum_n<kBlockSums, kScanThreads>(tot, ldsn);
+  if (threadIdx.x < kBlockSums) {
+    uint64_t x = tot[0];
+#pragma unroll
+    for (int k = 1; k < kBlockSums; ++k)
+      if ((int)threadIdx.x == k) x = tot[k];
+    group_sums[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = x;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void plan_prefix_kernel(
+    const uint64_t* __restrict__ block_sums, uint32_t nblocks, const uint64_t* __restrict__ group_sums,
+    uint64_t cap_tasks, uint64_t cap_accs, uint32_t min_j, uint32_t max_j, uint64_t target_tasks,
+    uint64_t* __restrict__ block_pre, uint32_t* __restrict__ ctl) {
+  constexpr int NP = kPlanPre;
+  __shared__ uint64_t ldsn[kScanThreads / 64][kBlockSums];
+  __shared__ uint64_t ldsp[kScanThreads / 64][NP];
+  __shared__ uint64_t ldsx[kScanThreads / 64][NP];
+  const uint32_t ngroups = gridDim.x, g = blockIdx.x;
+  // totals over every run (the runs' sums are few: one load per thread)
+  uint64_t tot[kBlockSums];
+#pragma unroll
+  for (int k = 0; k < kBlockSums; ++k) tot[k] = 0;
+  for (uint32_t i = threadIdx.x; i < ngroups; i += kScanThreads)
+#pragma unroll
+    for (int k = 0; k < kBlockSums; ++k) tot[k] += group_sums[(uint64_t)k * ngroups + i];
+  block_sum_n<kBlockSums, kScanThreads>(tot, ldsn);
   int jsel;
   uint64_t bucket;
-  plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, threadIdx.x == 0, ctl, jsel, bucket);
-  if (jsel < 0) return;  // uniform over the workgroup
-  // prefixes: rounds of 256 blocks per wave, lane l taking blocks 4l .. 4l + 3
-  // of the round (the next round's values load during this one's scan)
-  const uint64_t* col[NP];
-  uint64_t carry[NP], x[NP][4];
+  plan_choose(tot, cap_tasks, cap_accs, min_j, max_j, target_tasks, g == 0 && threadIdx.x == 0, ctl, jsel, bucket);
+  if (jsel < 0) return;  // uniform over the grid
+  int col[NP];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int c = k < kPlanSums ? jsel * kPlanSums + k : k == kPlanSums ? kSumTiny : kSumSmall;
-    col[k] = block_sums + (uint64_t)c * nblocks;
-    carry[k] = wave_sum64(lane < w ? ldsn[lane][c] : 0);  // the earlier waves' blocks
+  for (int k = 0; k < NP; ++k) col[k] = k < kPlanSums ? jsel * kPlanSums + k : k == kPlanSums ? kSumTiny : kSumSmall;
+  // the runs before this one
+  uint64_t pre[NP];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[k][i] = r0 + 4 * lane + i < r1 ? col[k][r0 + 4 * lane + i] : 0;
-  }
-  for (uint32_t b0 = r0; b0 < r1; b0 += 256) {  // uniform over the wave
-    const uint32_t b = b0 + 4 * lane, bn = b + 256;
-    uint64_t nx[NP][4];
+  for (int k = 0; k < NP; ++k) pre[k] = 0;
+  for (uint32_t i = threadIdx.x; i < g; i += kScanThreads)
 #pragma unroll
-    for (int k = 0; k < NP; ++k)
+    for (int k = 0; k < NP; ++k) pre[k] += group_sums[(uint64_t)col[k] * ngroups + i];
+  block_sum_n<NP, kScanThreads>(pre, ldsp);
+  uint32_t r0, r1;
+  scan_run(nblocks, ngroups, g, r0, r1);
+  for (uint32_t b0 = r0; b0 < r1; b0 += kScanThreads) {  // uniform over the workgroup
+    const uint32_t b = b0 + threadIdx.x;
+    uint64_t x[NP], run[NP];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) nx[k][i] = bn + i < r1 ? col[k][bn + i] : 0;
+    for (int k = 0; k < NP; ++k) x[k] = b < r1 ? block_sums[(uint64_t)col[k] * nblocks + b] : 0;
+    block_exclusive_n<NP, kScanThreads>(x, ldsx, run);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      const uint64_t mine = x[k][0] + x[k][1] + x[k][2] + x[k][3];
-      uint64_t inc = mine;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = shfl64(inc, lane >= d ? lane - d : lane);
-        if (lane >= d) inc += y;
-      }
-      uint64_t run = carry[k] + inc - mine;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (b + i < r1) block_pre[(uint64_t)k * nblocks + b + i] = run;
-        run += x[k][i];
-        x[k][i] = nx[k][i];
-      }
-      carry[k] += shfl64(inc, 63);
+      if (b < r1) block_pre[(uint64_t)k * nblocks + b] = pre[k] + x[k];
+      pre[k] += run[k];
     }
   }
 }
@@ -1538,6 +1584,127 @@ __global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
   }
 }
 
+// Composition of HalftimeHash with a short-input family (§1: a universe-
+// collapsing family reduces long strings to short values that a short-input
+// family hashes as if they were the input; §7: pairing HalftimeHash with a
+// fast short-input family).  The short-input family is simple tabulation:
+// C + 1 byte characters, one table of 256 random words per character, the
+// result the XOR of the characters' entries.  A string of at most C bytes is
+// its own key (zero-padded, separator character = its length); a longer
+// string's key is its C-byte HalftimeHash value with separator 255.
+//
+// One workgroup of kTabThreads per resident slot shares one LDS copy of the
+// tables ((C + 1) * 2 KiB) and of the Toeplitz tail and length keys; its
+// threads take strings with a grid stride.  A string of at most kTabInline
+// bytes is keyed here from its own bytes: as they are (at most C bytes), or
+// through its HalftimeHash value, which for a string shorter than one
+// execution is the tail and length terms alone (§6.1; at most 8 words); a
+// longer string's value comes from h.  Bytes are read as the aligned 8-byte
+// words that hold them (never a word without one of the string's bytes, so
+// never past the page of its allocation) and shifted into place.  Two-deep
+// pipeline: while string i is tabulated, the words (or the h row) of string
+// i + stride and the offset and length of string i + 2 stride are in flight.
+template <int C, int B>
+__global__ __launch_bounds__(kTabThreads) void tab_kernel(TabArgs a) {
+  using Ly = Layout<C, B>;
+  constexpr int K = Family<C>::K;
+  constexpr int NA = kTabInline / 8 + 1;  // aligned words that hold kTabInline bytes at any alignment
+  constexpr int NTAIL = (int)(Ly::len + K - Ly::tail);
+  static_assert(K * 8 == C, "one output word per 8 bytes");
+  static_assert(kTabInline < (uint32_t)Ly::exec_bytes, "inline strings are tail-only");
+  static_assert(NA >= K + 1, "a direct key's words");
+  __shared__ uint64_t T[(C + 1) * 256];
+  __shared__ uint64_t ltail[NTAIL];
+  for (int i = threadIdx.x; i < (C + 1) * 256; i += kTabThreads) T[i] = a.tables[i];
+  for (int i = threadIdx.x; i < NTAIL; i += kTabThreads) ltail[i] = a.ent[Ly::tail + i];
+  const uint64_t stride = (uint64_t)gridDim.x * kTabThreads;
+  struct Meta {
+    uint64_t L = 0, off = 0;
+  };
+  auto fetch = [&](uint64_t i, Meta& m) {
+    if (i < a.count) {
+      m.L = a.lengths[i];
+      m.off = a.offsets[i];
+    }
+  };
+  // the aligned words of an inline string, or the h row of a longer one
+  auto words_of = [&](uint64_t i, const Meta& m, uint64_t (&A)[NA]) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) A[j] = 0;
+    if (i >= a.count) return;
+    if (m.L > kTabInline) {
+      const uint64_t* h = reinterpret_cast<const uint64_t*>(a.h + i * C);
+#pragma unroll
+      for (int j = 0; j < K; ++j) A[j] = h[j];
+    } else if (m.L) {
+      const uintptr_t p = reinterpret_cast<uintptr_t>(a.bytes + m.off);
+      const uint64_t* w = reinterpret_cast<const uint64_t*>(p & ~(uintptr_t)7);
+      const uint64_t last = ((p & 7) + m.L - 1) / 8;
+#pragma unroll
+      for (int j = 0; j < NA; ++j)
+        if ((uint64_t)j <= last) A[j] = w[j];
+    }
+  };
+  uint64_t s = (uint64_t)blockIdx.x * kTabThreads + threadIdx.x;
+  Meta m0, m1;
+  fetch(s, m0);
+  fetch(s + stride, m1);
+  uint64_t A0[NA];
+  words_of(s, m0, A0);
+  __syncthreads();
+  for (; s < a.count; s += stride) {
+    Meta m2;
+    fetch(s + 2 * stride, m2);
+    uint64_t A1[NA];
+    words_of(s + stride, m1, A1);
+    const uint64_t L = m0.L;
+    uint64_t w[K];
+    uint32_t sep = 255;
+    if (L > kTabInline) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) w[j] = A0[j];
+    } else {
+      // word j of the string (bytes 8j .. 8j + 7, zero past its end)
+      const uint32_t sh = 8 * (uint32_t)(reinterpret_cast<uintptr_t>(a.bytes + m0.off) & 7);
+      auto word = [&](int j) -> uint64_t {
+        if (8 * (uint64_t)j >= L) return 0;
+        uint64_t x = sh ? (A0[j] >> sh) | (A0[j + 1] << (64 - sh)) : A0[j];
+        const uint64_t rem = L - 8 * (uint64_t)j;
+        if (rem < 8) x &= (1ull << (8 * rem)) - 1;
+        return x;
+      };
+      if (L <= (uint64_t)C) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) w[j] = word(j);
+        sep = (uint32_t)L;
+      } else {
+        // tail-only HalftimeHash value: Toeplitz tail words, then the length
+        uint64_t F[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) F[t] = 0;
+#pragma unroll
+        for (int j = 0; j < NA - 1; ++j) {
+          if (8 * (uint64_t)j < L) {
+            const uint64_t x = word(j);
+#pragma unroll
+            for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], x, ltail[t + j]);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t) w[t] = nh_acc(F[t], L, ltail[Ly::len - Ly::tail + t]);
+      }
+    }
+    uint64_t z = T[C * 256 + sep];
+#pragma unroll
+    for (int i = 0; i < C; ++i) z ^= T[i * 256 + (uint32_t)((w[i / 8] >> (8 * (i % 8))) & 0xFF)];
+    a.out[s] = z;
+    m0 = m1;
+    m1 = m2;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) A0[j] = A1[j];
+  }
+}
+
 // ROOTS: root mode (streaming): every string is a block of exactly 8^L
 // executions and its root node goes to a.roots instead of a hash to a.out.
 template <int WIDTH, int B, bool ROOTS>
@@ -2170,6 +2337,22 @@ const void* small_kernel_fn(uint32_t width, uint32_t block) {
   return f;
 }
 
+const void* tab_kernel_fn(uint32_t width, uint32_t block) {
+  const void* f = nullptr;
+  HTH_DISPATCH(width, block, f = reinterpret_cast<const void*>(&tab_kernel<W, Bk>));
+  return f;
+}
+
+hipError_t launch_tab(uint32_t width, uint32_t block, const TabArgs& a, uint32_t grid, hipStream_t stream) {
+  bool known = false;
+  HTH_DISPATCH(width, block, {
+    hipLaunchKernelGGL((tab_kernel<W, Bk>), dim3(grid), dim3(kTabThreads), 0, stream, a);
+    known = true;
+  });
+  if (!known) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 uint32_t exec_bytes_of(uint32_t width, uint32_t block) {
   uint32_t x = 0;
   HTH_DISPATCH(width, block, x = Layout<W, Bk>::exec_bytes);
@@ -2199,8 +2382,13 @@ hipError_t launch_plan(const PlanArgs& p, hipStream_t stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (scan) {
-    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, p.block_sums, nblocks, p.cap_tasks,
-                       p.cap_accs, p.min_j, p.max_j, p.target_tasks, p.block_pre, p.ctl);
+    uint32_t ngroups = (nblocks + kScanGroupMin - 1) / kScanGroupMin;
+    if (ngroups > kScanGroups) ngroups = kScanGroups;
+    hipLaunchKernelGGL(plan_group_kernel, dim3(ngroups), dim3(kScanThreads), 0, stream, p.block_sums, nblocks,
+                       p.group_sums);
+    hipLaunchKernelGGL(plan_prefix_kernel, dim3(ngroups), dim3(kScanThreads), 0, stream, p.block_sums, nblocks,
+                       (const uint64_t*)p.group_sums, p.cap_tasks, p.cap_accs, p.min_j, p.max_j, p.target_tasks,
+                       p.block_pre, p.ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

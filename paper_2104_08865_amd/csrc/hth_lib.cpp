@@ -94,6 +94,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   size_t o_ctl = take(hth::kCtlWords * 4);
   size_t o_bs = take(n.cap_blocks * hth::kBlockSums * 8);
   size_t o_bp = take(n.cap_blocks * hth::kPlanPre * 8);
+  size_t o_gs = take((size_t)hth::kScanGroups * hth::kBlockSums * 8);
   size_t o_ts = take(n.cap_tasks * 4);
   size_t o_st = take(n.cap_count * 4);
   size_t o_as = take(n.cap_count * 4);
@@ -118,6 +119,7 @@ hth_status ws_alloc(Workspace& w, uint64_t count, hipStream_t stream) {
   n.ctl = reinterpret_cast<uint32_t*>(b + o_ctl);
   n.block_sums = reinterpret_cast<uint64_t*>(b + o_bs);
   n.block_pre = reinterpret_cast<uint64_t*>(b + o_bp);
+  n.group_sums = reinterpret_cast<uint64_t*>(b + o_gs);
   n.task_string = reinterpret_cast<uint32_t*>(b + o_ts);
   n.task_start = reinterpret_cast<uint32_t*>(b + o_st);
   n.acc_start = reinterpret_cast<uint32_t*>(b + o_as);
@@ -298,6 +300,7 @@ hth_status enqueue_batch(const hth_seed* seed, const uint8_t* bytes, const uint6
   p.small_max = roots ? 0 : hth::kSmallMax;
   p.block_sums = w.block_sums;
   p.block_pre = w.block_pre;
+  p.group_sums = w.group_sums;
   p.cap_tasks = w.cap_tasks;
   p.cap_accs = w.cap_accs;
   p.min_j = tune.min_j;

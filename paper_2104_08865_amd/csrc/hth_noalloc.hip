@@ -29,7 +29,8 @@ constexpr size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t kOffCtl = 0;
 constexpr size_t kOffBs = kOffCtl + up256(hth::kCtlWords * 4);
 constexpr size_t kOffBp = kOffBs + up256(kNaBlocks * hth::kBlockSums * 8);
-constexpr size_t kOffTs = kOffBp + up256(kNaBlocks * hth::kPlanPre * 8);
+constexpr size_t kOffGs = kOffBp + up256(kNaBlocks * hth::kPlanPre * 8);
+constexpr size_t kOffTs = kOffGs + up256((size_t)hth::kScanGroups * hth::kBlockSums * 8);
 constexpr size_t kOffSt = kOffTs + up256(kNaTasks * 4);
 constexpr size_t kOffAs = kOffSt + up256(kNaCount * 4);
 constexpr size_t kOffTl = kOffAs + up256(kNaCount * 4);
@@ -88,6 +89,7 @@ Workspace na_workspace(uint8_t* b) {
   w.ctl = reinterpret_cast<uint32_t*>(b + kOffCtl);
   w.block_sums = reinterpret_cast<uint64_t*>(b + kOffBs);
   w.block_pre = reinterpret_cast<uint64_t*>(b + kOffBp);
+  w.group_sums = reinterpret_cast<uint64_t*>(b + kOffGs);
   w.task_string = reinterpret_cast<uint32_t*>(b + kOffTs);
   w.task_start = reinterpret_cast<uint32_t*>(b + kOffSt);
   w.acc_start = reinterpret_cast<uint32_t*>(b + kOffAs);
