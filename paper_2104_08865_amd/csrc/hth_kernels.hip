@@ -864,6 +864,7 @@ typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;  // the buffer, as an LDS pointer
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(3))) u32x4 lds_u4;
+typedef const __attribute__((address_space(3))) uint32_t lds_u32;
 constexpr int kLoadNT = 2;  // cache policy of the copies: non-temporal
 
 template <int WIDTH, int B>
@@ -927,6 +928,20 @@ __device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F)
 // slot positions cA - C0 ..  Padding, blocks of the other part and executions
 // past nq are not copied.  UNI: a full pass's region, whose G executions lie
 // a multiple of 128 bytes apart (same line alignment, one cA for all).
+//
+// The copies read from 4-byte-aligned addresses: when the executions start sh
+// = base mod 4 bytes past a 4-byte boundary (the same sh for all: they lie
+// multiples of 64 bytes apart), slot byte w holds execution byte w - sh of the
+// part, one more piece is copied at the part's end, and read_slot shifts the
+// bytes back into place.  (A direct-to-LDS copy from an address that is not a
+// multiple of 4 costs far more than one from an aligned address, and so does
+// an LDS read at such an offset: strings packed back to back took 1.18-1.20
+// ms either way where the same strings on 8-byte boundaries took 1.03.)  The
+// pieces copied lie in 4-byte-aligned words that hold bytes of the
+// executions, so never past the page of the string's allocation; such
+// strings start mid-block, so cA = C0 and no blocks are carried (cin = cout
+// = 0), and the slots' padding (at least one block past each part) holds the
+// extra piece.
 template <int WIDTH, int B, bool PART_B, bool UNI>
 __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uint32_t qs, uint32_t nq,
                                            uint32_t cnt, lds_u8* stage) {
@@ -936,6 +951,9 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
   constexpr uint32_t FIRST = PART_B ? P::C0 : 0;  // block at slot position 0
   // copied bytes of a slot: [wlo, whi) (uniform when UNI)
   const uint32_t ca_u = UNI ? part_a_blocks<WIDTH, B>(base) : 0;
+  const uint32_t sh = (uint32_t)reinterpret_cast<uintptr_t>(base) & 3u;  // (uniform)
+  const uint8_t* const abase = base - sh;
+  const uint32_t wext = sh ? 16u : 0u;
   const uint32_t lane = opaque_lane();
 #pragma unroll
   for (int i = 0; i < (int)S; ++i) {
@@ -944,22 +962,36 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
     const uint32_t ca = UNI ? ca_u : part_a_blocks<WIDTH, B>(base + q * qs);
     const uint32_t wlo = (PART_B ? ca - P::C0 : cnt) * P::BB;
     const uint32_t whi = PART_B ? (P::NBLK - P::C0 + cnt) * P::BB : ca * P::BB;
-    if (w >= wlo && w < whi && (UNI || q < nq))
-      __builtin_amdgcn_global_load_lds((const void*)(base + (q * qs + FIRST * P::BB + w)),
+    if (w >= wlo && w < whi + wext && (UNI || q < nq))
+      __builtin_amdgcn_global_load_lds((const void*)(abase + (q * qs + FIRST * P::BB + w)),
                                        (lds_void_ptr)(stage + 1024 * i), 16, 0, kLoadNT);
   }
 }
 
-// This lane's instance pair of N blocks of its execution's slot (S blocks).
+// This lane's instance pair of N blocks of its execution's slot (S blocks),
+// whose bytes start sh < 4 bytes into the slot (see stage_part): an aligned
+// 16-byte read and the next word, shifted right by sh bytes (bytes read past
+// the slot's copied ones are not used; the stage buffer has a guard word
+// past its last slot).
 template <int B, int N, int S>
-__device__ __forceinline__ void read_slot(const lds_u8* stage, uint4 (&x)[N]) {
+__device__ __forceinline__ void read_slot(const lds_u8* stage, uint32_t sh, uint4 (&x)[N]) {
   const uint32_t lane = opaque_lane();
   const int q = lane / Geo<B>::LPB, r = lane % Geo<B>::LPB;
   const lds_u8* at = stage + q * (S * 8 * B) + 16 * r;
+  if (sh == 0) {  // (uniform) aligned strings: one read per block
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const u32x4 v = *(lds_u4*)(at + 8 * B * k);
-    x[k] = make_uint4(v.x, v.y, v.z, v.w);
+    for (int k = 0; k < N; ++k) {
+      const u32x4 v = *(lds_u4*)(at + 8 * B * k);
+      x[k] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const u32x4 v = *(lds_u4*)(at + 8 * B * k);
+      const uint32_t e = *(lds_u32*)(at + 8 * B * k + 16);
+      x[k] = make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh), __builtin_amdgcn_alignbyte(v.z, v.y, sh),
+                        __builtin_amdgcn_alignbyte(v.w, v.z, sh), __builtin_amdgcn_alignbyte(e, v.w, sh));
+    }
   }
 }
 
@@ -1013,11 +1045,12 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
   Ehc<WIDTH> s;
   ehc_begin(s);
   const uint32_t ca = part_a_blocks<WIDTH, B>(base + (opaque_lane() / Geo<B>::LPB) * qs);
+  const uint32_t sh = (uint32_t)reinterpret_cast<uintptr_t>(base) & 3u;
   uint4 xe[LX > 0 ? LX : 1];  // part A's copies of blocks C0 .. C0+LX-1
   {
     uint4 x[P::NA];
     wait_vm();
-    read_slot<B, P::NA, P::SA>(stage, x);
+    read_slot<B, P::NA, P::SA>(stage, sh, x);
     wait_lgkm();
     stage_part<WIDTH, B, true, UNI>(base, qs, nq, cout, stage);
     if (call_hook) hook();  // (e.g. the string's tail loads, in flight with part B)
@@ -1031,7 +1064,7 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
   {
     uint4 x[P::NB];
     wait_vm();
-    read_slot<B, P::NB, P::SB>(stage, x);
+    read_slot<B, P::NB, P::SB>(stage, sh, x);
     wait_lgkm();
     stage_issue<WIDTH, B>(next, ncin, stage);
 #pragma unroll
@@ -1725,7 +1758,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ uint64_t lfin[K * NT0 * B];
   __shared__ uint64_t ltail[NTAIL];
   // this wave's region of staged executions
-  __shared__ __attribute__((aligned(1024))) uint8_t stage_buf[Parts<WIDTH, B>::BYTES];
+  __shared__ __attribute__((aligned(1024))) uint8_t stage_buf[Parts<WIDTH, B>::BYTES + 16];  // (+ guard, read_slot)
   lds_u8* const stage = (lds_u8*)stage_buf;
 
   const int lane = threadIdx.x;
