@@ -300,15 +300,20 @@ def run_throughput(args):
 
 
 SERVE_LOADS = (0.25, 0.5, 0.8)
-SERVE_CLIENTS = 4  # replay threads submitting (copies into the staging overlap)
+SERVE_CLIENTS = 4  # replay threads of the staged submits (their copies into the staging overlap)
+SERVE_PINNED_CLIENTS = 1  # replay thread of the pinned submits (no copy; one receiving thread)
 
 
 def serve_legs(n_req, verify=False):
     """The serving workload: lognormal request lengths (median 4 KiB,
     sigma 2, capped at 16 MiB), widths 16/40 at 50/50, bytes from splitmix64
-    seed 5, replayed from host memory into one server.  First at no pacing
-    (every request due at once) to measure the server's capacity, then with
-    Poisson arrivals at 0.25, 0.5 and 0.8 of that capacity."""
+    seed 5, replayed from pinned host memory into one server
+    (hth_serve_replay_pinned: the requests' bytes are copied to the device by
+    the server's batches, with no staging copy).  First at no pacing (every
+    request due at once) to measure the server's capacity, then with Poisson
+    arrivals at 0.25, 0.5 and 0.8 of that capacity; the capacity of the
+    staged submit path (bytes copied into the server's pinned staging by the
+    client threads) is reported beside it."""
     import torch
     from paper_2104_08865_amd import hth
     from paper_2104_08865_amd import workloads as wl
@@ -319,16 +324,29 @@ def serve_legs(n_req, verify=False):
     offs, total = wl.pack(lens)
     log(f"[bench] serving: {n_req} requests, {total} bytes, mean {total / n_req:.0f} B")
     data = wl.random_bytes(5, total)
+    pinned = hth.pinned_bytes(data)
     seed = hth.expand_seed(5)
     torch.cuda.synchronize()
     res = {"workload": "serving: lognormal lengths (median 4 KiB, sigma 2, cap 16 MiB), widths 16/40 50/50, "
-                       "bytes splitmix64 seed 5, submitted from host memory; Poisson arrivals",
-           "requests_per_load": n_req, "mean_request_bytes": total / n_req, "client_threads": SERVE_CLIENTS,
+                       "bytes splitmix64 seed 5, submitted from pinned host memory; Poisson arrivals",
+           "requests_per_load": n_req, "mean_request_bytes": total / n_req, "client_threads": SERVE_PINNED_CLIENTS,
+           "client_threads_staged": SERVE_CLIENTS,
            "loads": []}
     with hth.Server(seed, max_device_bytes=2 << 30, host_stage_bytes=2 << 30) as srv:
-        # capacity: every request due at once
+        # the staged submit path's capacity (client threads copy into staging)
         tickets = srv.replay(data, offs, lens, widths, np.zeros(n_req, dtype=np.uint64), threads=SERVE_CLIENTS)
+        staged = srv.wait_many(tickets)
+        st = srv.stats()
+        res["capacity_staged_submit"] = {"requests_per_s": st["completed"] / st["elapsed_s"], "GBps": st["gbps"],
+                                         "p50_us": st["latency_p50_us"], "p99_us": st["latency_p99_us"],
+                                         "mean_batch_requests": st["mean_batch_requests"]}
+        log(f"[bench] serving capacity, staged submits: {st['gbps']:.1f} GB/s")
+        srv.reset_stats()
+        # capacity: every request due at once
+        tickets = srv.replay(pinned, offs, lens, widths, np.zeros(n_req, dtype=np.uint64),
+                             threads=SERVE_PINNED_CLIENTS, pinned=True)
         got = srv.wait_many(tickets)
+        res["staged_equals_pinned"] = bool((staged == got).all())
         res["oracle_spot_check"] = _serve_spot_check(data, offs, lens, widths, got)
         st = srv.stats()
         cap_rps = st["completed"] / st["elapsed_s"]
@@ -339,7 +357,7 @@ def serve_legs(n_req, verify=False):
             rate = load * cap_rps
             arrive = (np.cumsum(unit_gaps) / rate * 1e9).astype(np.uint64)
             srv.reset_stats()
-            tickets = srv.replay(data, offs, lens, widths, arrive, threads=SERVE_CLIENTS)
+            tickets = srv.replay(pinned, offs, lens, widths, arrive, threads=SERVE_PINNED_CLIENTS, pinned=True)
             out = srv.wait_many(tickets)
             st = srv.stats()
             same = bool((out == got).all())

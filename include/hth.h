@@ -333,7 +333,7 @@ hth_status hth_stream_free(hth_stream *st);
 /* batches (continuous batching: a batch leaves as soon as a stream slot is */
 /* free) and hashes every batch with the planner and kernel of             */
 /* hth_hash_batch, so a request's value does not depend on what it was     */
-/* batched with.  A worker thread per server does the scheduling.           */
+/* batched with.  A thread per stream slot does the scheduling.             */
 /* ------------------------------------------------------------------------ */
 
 typedef struct hth_server hth_server;
@@ -369,8 +369,9 @@ typedef struct hth_serve_report {
 } hth_serve_report;
 
 /* Create a server on the current device for `seed` (which must outlive it).
-   Allocates the device budget, the pinned staging, per-slot streams and
-   workspaces, and starts the worker thread.  Unset (zero) fields take the
+   Allocates the device budget, the pinned staging (every page touched once,
+   so that submits do not fault on them), per-slot streams and workspaces,
+   and starts one thread per slot.  Unset (zero) fields take the
    defaults above.  Errors: HTH_E_INVALID (null pointer, limits out of range
    or inconsistent, seed on another device), HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_serve_create(const hth_serve_config *config, const hth_seed *seed, hth_server **out);
@@ -384,6 +385,18 @@ hth_status hth_serve_create(const hth_serve_config *config, const hth_seed *seed
    later), HTH_E_INVALID, HTH_E_HIP (the server stopped after an error). */
 hth_status hth_serve_submit(hth_server *server, const void *host_bytes, uint64_t len, uint32_t out_width,
                             uint64_t *ticket);
+
+/* Submit one request whose bytes stay in the caller's pinned host memory
+   (hipHostMalloc, or a pinned torch tensor): nothing is copied at submit;
+   the server's batch copies them to the device directly.  The caller must
+   leave the `len` bytes unchanged and allocated until the ticket's result
+   has been collected.  Requests submitted back to back from consecutive
+   bytes are copied to the device together.  Otherwise as hth_serve_submit
+   (HTH_E_BUSY only for max_outstanding: no staging is used).  For callers
+   whose requests already arrive in pinned memory (e.g. network receive
+   buffers), the submit path without the staging copy. */
+hth_status hth_serve_submit_pinned(hth_server *server, const void *pinned_bytes, uint64_t len, uint32_t out_width,
+                                   uint64_t *ticket);
 
 /* Collect a result without blocking: HTH_OK copies out_width bytes to
    out_host and retires the ticket; HTH_E_BUSY means not ready yet;
@@ -409,6 +422,12 @@ hth_status hth_serve_replay(hth_server *server, const uint8_t *base, const uint6
                             const uint64_t *lengths, const uint32_t *widths, const uint64_t *arrival_ns,
                             uint64_t n, uint32_t threads, uint64_t *tickets);
 
+/* As hth_serve_replay, submitting with hth_serve_submit_pinned: base must
+   be pinned host memory, unchanged until every result is collected. */
+hth_status hth_serve_replay_pinned(hth_server *server, const uint8_t *base, const uint64_t *offsets,
+                                   const uint64_t *lengths, const uint32_t *widths, const uint64_t *arrival_ns,
+                                   uint64_t n, uint32_t threads, uint64_t *tickets);
+
 /* Hold (paused != 0) or release (0) batching: while held, submitted
    requests queue up (within the staging and outstanding limits) and no new
    batch starts; batches already in flight complete.  For bursts that should
@@ -419,7 +438,7 @@ hth_status hth_serve_pause(hth_server *server, int32_t paused);
 hth_status hth_serve_stats(hth_server *server, hth_serve_report *out);
 hth_status hth_serve_reset_stats(hth_server *server);
 
-/* Stop the worker (after the batches in flight complete) and free the
+/* Stop the slot threads (after the batches in flight complete) and free the
    server; uncollected results are dropped.  Null is accepted. */
 hth_status hth_serve_destroy(hth_server *server);
 

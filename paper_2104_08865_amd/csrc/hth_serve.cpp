@@ -5,7 +5,8 @@
 // from the HIP kernels.
 //
 // Data path of one request:
-//   submit:  bytes copied into a pinned host ring (FIFO allocation);
+//   submit:  bytes copied into a pinned host ring (FIFO allocation), or, for
+//            hth_serve_submit_pinned, left in the caller's pinned memory;
 //   slot:    admitted when the device ring (the memory budget) has room,
 //            packed with the other admitted requests into a batch, copied
 //            host ring -> device ring on the slot's stream, hashed (one
@@ -94,7 +95,14 @@ struct Request {
   uint32_t width;
   bool deferred;
   Clock::time_point t_submit;
+  const uint8_t* src;  // caller's pinned bytes (hth_serve_submit_pinned), else null: in the host ring
 };
+
+// Bytes a request takes in the device ring: a staged request keeps its
+// 256-byte padding (runs contiguous in both rings are one copy); a pinned
+// one takes exactly its length, so that requests contiguous in the caller's
+// memory are contiguous on the device too and go in one copy.
+uint64_t dev_bytes(const Request& r) { return r.src ? r.len : pad(r.len); }
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -198,7 +206,7 @@ bool admit_locked(hth_server* s, Slot& sl) {
     if (!s->copied[r.ticket & s->mask].load()) break;  // bytes still being copied
     if (!sl.reqs.empty() && bytes + r.len > s->cfg.max_batch_bytes) break;
     uint64_t pos = 0;
-    if (!s->dev.alloc(pad(r.len), &pos)) {
+    if (!s->dev.alloc(dev_bytes(r), &pos)) {
       // device budget exhausted: the request waits for a batch to retire
       if (!r.deferred) {
         r.deferred = true;
@@ -214,12 +222,53 @@ bool admit_locked(hth_server* s, Slot& sl) {
   }
   if (sl.reqs.empty()) return false;
   sl.seq = s->next_seq++;
-  s->inflight.push_back(Inflight{sl.seq, sl.reqs.back().host_pos + pad(sl.reqs.back().len), s->dev.head, false});
+  // host ring space up to the end of the batch's last staged request (none:
+  // nothing to release)
+  uint64_t host_end = 0;
+  for (const Request& r : sl.reqs)
+    if (!r.src) host_end = r.host_pos + pad(r.len);
+  s->inflight.push_back(Inflight{sl.seq, host_end, s->dev.head, false});
   return true;
+}
+
+// Pinned requests take their device ring bytes in admission order, but
+// requests from several client threads arrive interleaved, so neighbours in
+// the caller's memory are rarely neighbours in the queue.  Each run of
+// pinned requests that is contiguous in the device ring is laid out again in
+// the order of their host addresses (the same bytes of the ring, so nothing
+// else changes), which makes requests adjacent in host memory adjacent on
+// the device: one copy for each run of them.
+void sort_pinned_runs(hth_server* s, Slot& sl) {
+  std::vector<Request>& q = sl.reqs;
+  size_t i = 0;
+  while (i < q.size()) {
+    if (!q[i].src) {
+      ++i;
+      continue;
+    }
+    size_t j = i + 1;
+    uint64_t end = q[i].dev_pos + q[i].len;
+    while (j < q.size() && q[j].src && q[j].dev_pos == end && (q[i].dev_pos % s->dev.cap) + (end - q[i].dev_pos) +
+                                                                     q[j].len <= s->dev.cap) {
+      end += q[j].len;
+      ++j;
+    }
+    if (j - i > 1) {
+      const uint64_t d0 = q[i].dev_pos;
+      std::sort(q.begin() + i, q.begin() + j, [](const Request& a, const Request& b) { return a.src < b.src; });
+      uint64_t d = d0;
+      for (size_t k = i; k < j; ++k) {
+        q[k].dev_pos = d;
+        d += q[k].len;
+      }
+    }
+    i = j;
+  }
 }
 
 // Enqueues the admitted batch of slot `sl` on its stream (no lock held).
 bool launch_batch(hth_server* s, Slot& sl) {
+  sort_pinned_runs(s, sl);
   // group by width, in submission order inside each group
   uint64_t n[kWidths] = {};
   for (const Request& r : sl.reqs) ++n[widx(r.width)];
@@ -240,21 +289,21 @@ bool launch_batch(hth_server* s, Slot& sl) {
   }
 
   hipError_t e = hipSuccess;
-  // request bytes: runs contiguous in both rings become one copy
+  // request bytes: runs contiguous in host memory (the ring or the caller's)
+  // and in the device ring become one copy
+  auto src_of = [&](const Request& r) { return r.src ? r.src : s->h_ring + r.host_pos % s->host.cap; };
   size_t i = 0;
   while (i < sl.reqs.size() && e == hipSuccess) {
-    const uint64_t h0 = sl.reqs[i].host_pos, d0 = sl.reqs[i].dev_pos;
-    uint64_t len = pad(sl.reqs[i].len);
+    const uint8_t* h0 = src_of(sl.reqs[i]);
+    const uint64_t d0 = sl.reqs[i].dev_pos;
+    uint64_t len = dev_bytes(sl.reqs[i]);
     size_t j = i + 1;
-    while (j < sl.reqs.size() && sl.reqs[j].host_pos == h0 + len && sl.reqs[j].dev_pos == d0 + len &&
-           (h0 % s->host.cap) + len + pad(sl.reqs[j].len) <= s->host.cap &&
-           (d0 % s->dev.cap) + len + pad(sl.reqs[j].len) <= s->dev.cap) {
-      len += pad(sl.reqs[j].len);
+    while (j < sl.reqs.size() && src_of(sl.reqs[j]) == h0 + len && sl.reqs[j].dev_pos == d0 + len &&
+           (d0 % s->dev.cap) + len + dev_bytes(sl.reqs[j]) <= s->dev.cap) {
+      len += dev_bytes(sl.reqs[j]);
       ++j;
     }
-    if (len)
-      e = hipMemcpyAsync(s->d_ring + d0 % s->dev.cap, s->h_ring + h0 % s->host.cap, len, hipMemcpyHostToDevice,
-                         sl.stream);
+    if (len) e = hipMemcpyAsync(s->d_ring + d0 % s->dev.cap, h0, len, hipMemcpyHostToDevice, sl.stream);
     i = j;
   }
   if (e == hipSuccess) e = hipMemcpyAsync(sl.d_meta, sl.h_meta, meta * 8, hipMemcpyHostToDevice, sl.stream);
@@ -413,6 +462,111 @@ hth_status take(hth_server* s, uint64_t ticket, uint8_t* out, bool block) {
   return HTH_OK;
 }
 
+// Accepts one request: staged (copied into the host ring) or pinned (left
+// in the caller's memory until its batch's copy).
+hth_status submit(hth_server* s, const void* host_bytes, uint64_t len, uint32_t out_width, uint64_t* ticket,
+                  bool pinned) {
+  const Clock::time_point t0 = Clock::now();
+  const char* fn = pinned ? "hth_serve_submit_pinned" : "hth_serve_submit";
+  if (!s || !ticket) return fail(HTH_E_INVALID, "%s: null server or ticket", fn);
+  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "%s: out_width %u", fn, out_width);
+  if (len && !host_bytes) return fail(HTH_E_INVALID, "%s: host_bytes is null", fn);
+  if (len > s->cfg.max_request_bytes)
+    return fail(HTH_E_TOO_LARGE, "%s: %llu bytes above the limit %llu", fn, (unsigned long long)len,
+                (unsigned long long)s->cfg.max_request_bytes);
+  if (s->failed.load()) return server_error(s);
+  uint64_t t = 0, pos = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    t = s->next_ticket;
+    const uint64_t old_head = s->host.head, old_tail = s->host.tail;
+    bool ok = pinned || s->host.alloc(pad(len), &pos);
+    if (ok) {
+      std::lock_guard<std::mutex> rl(s->r_mu);
+      Entry& en = s->entries[t & s->mask];
+      if (en.state != kFree) {
+        ok = false;
+        s->host.head = old_head;  // undo: nothing was allocated after it
+        s->host.tail = old_tail;
+      } else {
+        en.ticket = t;
+        en.state = kPending;
+        en.width = (uint8_t)out_width;
+        ++s->n_submitted;
+        if (!s->have_first) {
+          s->have_first = true;
+          s->t_first = t0;
+        }
+      }
+    }
+    if (!ok) {
+      std::lock_guard<std::mutex> rl(s->r_mu);
+      ++s->n_busy;
+      return HTH_E_BUSY;
+    }
+    ++s->next_ticket;
+    s->copied[t & s->mask].store(pinned ? 1 : 0);
+    s->pending.push_back(
+        Request{t, pos, 0, len, out_width, false, t0, pinned ? static_cast<const uint8_t*>(host_bytes) : nullptr});
+    if (pinned && s->idle_slots.load()) s->q_cv.notify_one();
+  }
+  *ticket = t;
+  if (pinned) return HTH_OK;
+  if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
+  s->copied[t & s->mask].store(1);
+  if (s->idle_slots.load()) {
+    // the lock orders the notify after an idle slot's look at the queue
+    std::lock_guard<std::mutex> lk(s->q_mu);
+    s->q_cv.notify_one();
+  }
+  return HTH_OK;
+}
+
+// Load replay (hth_serve_replay, hth_serve_replay_pinned).
+hth_status replay(hth_server* s, const uint8_t* base, const uint64_t* offsets, const uint64_t* lengths,
+                  const uint32_t* widths, const uint64_t* arrival_ns, uint64_t n, uint32_t threads,
+                  uint64_t* tickets, bool pinned) {
+  if (!s || (n && (!base || !offsets || !lengths || !widths || !arrival_ns || !tickets)))
+    return fail(HTH_E_INVALID, "hth_serve_replay: null pointer");
+  if (threads == 0 || threads > 64) return fail(HTH_E_INVALID, "hth_serve_replay: threads %u not in 1..64", threads);
+  const Clock::time_point t0 = Clock::now();
+  std::atomic<int> first_err{HTH_OK};
+  std::string err_msg;
+  std::mutex err_mu;
+  // client k submits requests k, k + threads, ... at their arrival times
+  auto client = [&](uint32_t k) {
+    for (uint64_t i = k; i < n && first_err.load() == HTH_OK; i += threads) {
+      const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
+      while (Clock::now() < due) {
+      }
+      for (;;) {
+        hth_status st = submit(s, base + offsets[i], lengths[i], widths[i], tickets + i, pinned);
+        if (st == HTH_OK) break;
+        if (st != HTH_E_BUSY) {
+          std::lock_guard<std::mutex> lk(err_mu);
+          if (first_err.load() == HTH_OK) {
+            err_msg = hth_last_error();
+            first_err.store(st);
+          }
+          return;
+        }
+        std::this_thread::yield();  // staging full: wait for a batch to retire
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (uint32_t k = 1; k < threads; ++k) pool.emplace_back(client, k);
+  } catch (...) {
+    first_err.store(HTH_E_OOM);
+    err_msg = "replay thread";
+  }
+  client(0);
+  for (auto& th : pool) th.join();
+  if (first_err.load() != HTH_OK) return fail(first_err.load(), "hth_serve_replay: %s", err_msg.c_str());
+  return HTH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -517,56 +671,12 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
 
 hth_status hth_serve_submit(hth_server* s, const void* host_bytes, uint64_t len, uint32_t out_width,
                             uint64_t* ticket) {
-  const Clock::time_point t0 = Clock::now();
-  if (!s || !ticket) return fail(HTH_E_INVALID, "hth_serve_submit: null server or ticket");
-  if (!width_ok(out_width)) return fail(HTH_E_INVALID, "hth_serve_submit: out_width %u", out_width);
-  if (len && !host_bytes) return fail(HTH_E_INVALID, "hth_serve_submit: host_bytes is null");
-  if (len > s->cfg.max_request_bytes)
-    return fail(HTH_E_TOO_LARGE, "hth_serve_submit: %llu bytes above the limit %llu", (unsigned long long)len,
-                (unsigned long long)s->cfg.max_request_bytes);
-  if (s->failed.load()) return server_error(s);
-  uint64_t t = 0, pos = 0;
-  {
-    std::lock_guard<std::mutex> lk(s->q_mu);
-    t = s->next_ticket;
-    const uint64_t old_head = s->host.head, old_tail = s->host.tail;
-    bool ok = s->host.alloc(pad(len), &pos);
-    if (ok) {
-      std::lock_guard<std::mutex> rl(s->r_mu);
-      Entry& en = s->entries[t & s->mask];
-      if (en.state != kFree) {
-        ok = false;
-        s->host.head = old_head;  // undo: nothing was allocated after it
-        s->host.tail = old_tail;
-      } else {
-        en.ticket = t;
-        en.state = kPending;
-        en.width = (uint8_t)out_width;
-        ++s->n_submitted;
-        if (!s->have_first) {
-          s->have_first = true;
-          s->t_first = t0;
-        }
-      }
-    }
-    if (!ok) {
-      std::lock_guard<std::mutex> rl(s->r_mu);
-      ++s->n_busy;
-      return HTH_E_BUSY;
-    }
-    ++s->next_ticket;
-    s->copied[t & s->mask].store(0, std::memory_order_relaxed);
-    s->pending.push_back(Request{t, pos, 0, len, out_width, false, t0});
-  }
-  if (len) std::memcpy(s->h_ring + pos % s->host.cap, host_bytes, len);
-  s->copied[t & s->mask].store(1);
-  if (s->idle_slots.load()) {
-    // the lock orders the notify after an idle slot's look at the queue
-    std::lock_guard<std::mutex> lk(s->q_mu);
-    s->q_cv.notify_one();
-  }
-  *ticket = t;
-  return HTH_OK;
+  return submit(s, host_bytes, len, out_width, ticket, false);
+}
+
+hth_status hth_serve_submit_pinned(hth_server* s, const void* pinned_bytes, uint64_t len, uint32_t out_width,
+                                   uint64_t* ticket) {
+  return submit(s, pinned_bytes, len, out_width, ticket, true);
 }
 
 hth_status hth_serve_poll(hth_server* s, uint64_t ticket, uint8_t* out_host) {
@@ -593,45 +703,13 @@ hth_status hth_serve_wait_many(hth_server* s, const uint64_t* tickets, uint64_t 
 hth_status hth_serve_replay(hth_server* s, const uint8_t* base, const uint64_t* offsets, const uint64_t* lengths,
                             const uint32_t* widths, const uint64_t* arrival_ns, uint64_t n, uint32_t threads,
                             uint64_t* tickets) {
-  if (!s || (n && (!base || !offsets || !lengths || !widths || !arrival_ns || !tickets)))
-    return fail(HTH_E_INVALID, "hth_serve_replay: null pointer");
-  if (threads == 0 || threads > 64) return fail(HTH_E_INVALID, "hth_serve_replay: threads %u not in 1..64", threads);
-  const Clock::time_point t0 = Clock::now();
-  std::atomic<int> first_err{HTH_OK};
-  std::string err_msg;
-  std::mutex err_mu;
-  // client k submits requests k, k + threads, ... at their arrival times
-  auto client = [&](uint32_t k) {
-    for (uint64_t i = k; i < n && first_err.load() == HTH_OK; i += threads) {
-      const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
-      while (Clock::now() < due) {
-      }
-      for (;;) {
-        hth_status st = hth_serve_submit(s, base + offsets[i], lengths[i], widths[i], tickets + i);
-        if (st == HTH_OK) break;
-        if (st != HTH_E_BUSY) {
-          std::lock_guard<std::mutex> lk(err_mu);
-          if (first_err.load() == HTH_OK) {
-            err_msg = hth_last_error();
-            first_err.store(st);
-          }
-          return;
-        }
-        std::this_thread::yield();  // staging full: wait for a batch to retire
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  try {
-    for (uint32_t k = 1; k < threads; ++k) pool.emplace_back(client, k);
-  } catch (...) {
-    first_err.store(HTH_E_OOM);
-    err_msg = "replay thread";
-  }
-  client(0);
-  for (auto& th : pool) th.join();
-  if (first_err.load() != HTH_OK) return fail(first_err.load(), "hth_serve_replay: %s", err_msg.c_str());
-  return HTH_OK;
+  return replay(s, base, offsets, lengths, widths, arrival_ns, n, threads, tickets, false);
+}
+
+hth_status hth_serve_replay_pinned(hth_server* s, const uint8_t* base, const uint64_t* offsets,
+                                   const uint64_t* lengths, const uint32_t* widths, const uint64_t* arrival_ns,
+                                   uint64_t n, uint32_t threads, uint64_t* tickets) {
+  return replay(s, base, offsets, lengths, widths, arrival_ns, n, threads, tickets, true);
 }
 
 hth_status hth_serve_pause(hth_server* s, int32_t paused) {

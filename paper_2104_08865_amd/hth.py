@@ -33,8 +33,26 @@ SYMBOLS = (
     "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words", "hth_stream_create",
     "hth_stream_update", "hth_stream_final", "hth_stream_reset", "hth_stream_save", "hth_stream_load",
     "hth_stream_length", "hth_stream_free", "hth_tab_words", "hth_tab_expand", "hth_hash_batch64",
-    "hth_hash_batch_noalloc",
+    "hth_hash_batch_noalloc", "hth_serve_submit_pinned", "hth_serve_replay_pinned",
 )
+
+
+def _require_pinned(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.device.type == "cpu" and t.dtype == torch.uint8 and t.is_contiguous()
+            and (t.numel() == 0 or t.is_pinned())):
+        raise ValueError("expected a contiguous pinned CPU uint8 torch tensor")
+
+
+def pinned_bytes(data):
+    """A pinned CPU uint8 torch tensor holding a copy of `data` (a uint8 numpy
+    array or bytes), for Server.submit_pinned and Server.replay(pinned=True)."""
+    import torch
+    src = np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else np.asarray(data, np.uint8)
+    t = torch.empty(src.size, dtype=torch.uint8, pin_memory=True)
+    if src.size:
+        t.numpy()[:] = src
+    return t
 
 
 class ServeConfig(ctypes.Structure):
@@ -97,6 +115,8 @@ def lib():
         L.hth_serve_wait.argtypes = [vp, u64, vp]
         L.hth_serve_wait_many.argtypes = [vp, vp, u64, vp, u32]
         L.hth_serve_replay.argtypes = [vp, vp, vp, vp, vp, vp, u64, u32, vp]
+        L.hth_serve_submit_pinned.argtypes = [vp, vp, u64, u32, ctypes.POINTER(u64)]
+        L.hth_serve_replay_pinned.argtypes = [vp, vp, vp, vp, vp, vp, u64, u32, vp]
         L.hth_serve_stats.argtypes = [vp, ctypes.POINTER(ServeReport)]
         L.hth_serve_reset_stats.argtypes = [vp]
         L.hth_serve_destroy.argtypes = [vp]
@@ -407,6 +427,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().hth_serve_create(ctypes.byref(cfg), seed.handle, ctypes.byref(h)))
         self._h = h
+        self._pinned = []  # pinned buffers whose bytes requests may still read
 
     def submit(self, data, out_width):
         """Submit bytes (bytes, bytearray or a uint8 numpy array); returns
@@ -417,6 +438,22 @@ class Server:
         t = ctypes.c_uint64()
         rc = lib().hth_serve_submit(self._h, ctypes.c_void_p(buf.ctypes.data if buf.size else 0), buf.size,
                                     out_width, ctypes.byref(t))
+        if rc == HTH_E_BUSY:
+            return None
+        _check(rc)
+        return t.value
+
+    def submit_pinned(self, data, out_width):
+        """Submit the bytes of a pinned CPU uint8 torch tensor (contiguous)
+        without copying them: the server reads them when it hashes the
+        request, so the tensor must stay unchanged until the result is
+        collected (the server keeps a reference until it is closed).
+        Returns the ticket, or None when too many results are uncollected."""
+        _require_pinned(data)
+        self._pinned.append(data)
+        t = ctypes.c_uint64()
+        rc = lib().hth_serve_submit_pinned(self._h, ctypes.c_void_p(data.data_ptr() if data.numel() else 0),
+                                           data.numel(), out_width, ctypes.byref(t))
         if rc == HTH_E_BUSY:
             return None
         _check(rc)
@@ -445,19 +482,28 @@ class Server:
                                          ctypes.c_void_p(out.ctypes.data), 40))
         return out
 
-    def replay(self, base, offsets, lengths, widths, arrival_ns, threads=1):
+    def replay(self, base, offsets, lengths, widths, arrival_ns, threads=1, pinned=False):
         """Submit request i (base[offsets[i]:][:lengths[i]], widths[i]) at
         arrival_ns[i] after the call starts, from `threads` client threads;
-        returns the tickets."""
-        base = np.ascontiguousarray(base, dtype=np.uint8)
+        returns the tickets.  pinned: base is a pinned CPU uint8 torch
+        tensor whose bytes are hashed in place (hth_serve_replay_pinned; it
+        must stay unchanged until the results are collected), else bytes
+        are copied into the server's staging (any uint8 array)."""
+        if pinned:
+            _require_pinned(base)
+            self._pinned.append(base)
+            base_ptr = ctypes.c_void_p(base.data_ptr())
+        else:
+            base = np.ascontiguousarray(base, dtype=np.uint8)
+            base_ptr = ctypes.c_void_p(base.ctypes.data)
         o = np.ascontiguousarray(offsets, dtype=np.uint64)
         n = np.ascontiguousarray(lengths, dtype=np.uint64)
         w = np.ascontiguousarray(widths, dtype=np.uint32)
         a = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
         tickets = np.zeros(o.size, dtype=np.uint64)
         ptr = lambda x: ctypes.c_void_p(x.ctypes.data)
-        _check(lib().hth_serve_replay(self._h, ptr(base), ptr(o), ptr(n), ptr(w), ptr(a), o.size, threads,
-                                      ptr(tickets)))
+        fn = lib().hth_serve_replay_pinned if pinned else lib().hth_serve_replay
+        _check(fn(self._h, base_ptr, ptr(o), ptr(n), ptr(w), ptr(a), o.size, threads, ptr(tickets)))
         return tickets
 
     def pause(self, paused=True):
@@ -477,6 +523,7 @@ class Server:
             h, self._h = self._h, None
             _check(lib().hth_serve_destroy(h))
         self._h = None
+        self._pinned = []
 
     def __enter__(self):
         return self

@@ -200,3 +200,40 @@ def test_burst_from_many_threads(env, requests20k):
         sel = np.nonzero(widths == w)[0]
         ref = hth.hash_batch(env["seed"], d, o[torch.from_numpy(sel).cuda()], ln[torch.from_numpy(sel).cuda()], w)
         assert (got[sel, :w] == ref.cpu().numpy()).all()
+
+
+def test_pinned_requests_mixed_with_staged(env, requests20k):
+    """Requests left in the caller's pinned memory (hth_serve_submit_pinned,
+    including empty and one-byte ones at odd addresses) interleaved with
+    staged ones, then a pinned replay of 5,000 requests from 4 threads with
+    every request due at once under a 32 MiB device budget: every result
+    equals the oracle's."""
+    hth = env["hth"]
+    rq = requests20k
+    n = 600
+    lens = np.concatenate([rq["lens"][:n - 3] % (256 << 10), np.array([0, 1, 3], np.uint64)])
+    widths = np.concatenate([rq["widths"][:n - 3], np.array([24, 32, 40], np.uint32)])
+    offs, total = wl.pack(lens)
+    offs = offs + 1  # every request at an odd address of the pinned buffer
+    data = wl.random_bytes(11, total + 1)
+    pinned = hth.pinned_bytes(data)
+    print(f"[serve] pinned mix requests={n} bytes={total}", flush=True)
+    with hth.Server(env["seed"]) as srv:
+        tickets = []
+        for i in range(n):
+            o, ln, w = int(offs[i]), int(lens[i]), int(widths[i])
+            t = srv.submit_pinned(pinned[o:o + ln], w) if i % 3 else srv.submit(data[o:o + ln], w)
+            assert t is not None
+            tickets.append(t)
+        got = srv.wait_many(np.array(tickets, dtype=np.uint64))
+    assert (got == _oracle(env, data, offs, lens, widths)).all()
+
+    m = 5000
+    lens, widths, offs = rq["lens"][:m], rq["widths"][:m], rq["offs"][:m]
+    pinned = hth.pinned_bytes(rq["data"])
+    with hth.Server(env["seed"], max_device_bytes=32 << 20) as srv:
+        tickets = srv.replay(pinned, offs, lens, widths, np.zeros(m, dtype=np.uint64), threads=4, pinned=True)
+        got = srv.wait_many(tickets)
+        st = srv.stats()
+    assert st["completed"] == m
+    assert (got == _oracle(env, rq["data"], offs, lens, widths)).all()
