@@ -85,6 +85,21 @@ __device__ __forceinline__ key_ptr uniform_keys(const uint64_t* p) { return (key
 typedef const __attribute__((address_space(4))) uint32_t* meta32_ptr;
 __device__ __forceinline__ meta32_ptr smeta(const uint32_t* p) { return (meta32_ptr)p; }
 
+// The n bytes at p (1 <= n <= 7) as a zero-padded little-endian word: the
+// one or two aligned words that hold them, shifted into place (both loads
+// issued at once; each word holds one of the n bytes, so neither reaches
+// past the page of the bytes' allocation).  Byte-by-byte loads in a loop of
+// n iterations were waited for one after another.
+__device__ __forceinline__ uint64_t load_partial_word(const uint8_t* p, uint32_t n) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(a & ~(uintptr_t)7);
+  const uint32_t s = 8 * (uint32_t)(a & 7);
+  const uint64_t lo = w[0];
+  const uint64_t hi = (a & 7) + n > 8 ? w[1] : 0;
+  const uint64_t v = s ? (lo >> s) | (hi << (64 - s)) : lo;
+  return v & ((1ull << (8 * n)) - 1);
+}
+
 __device__ __forceinline__ uint4 load16(const uint8_t* p) {
   uint4 v;
   __builtin_memcpy(&v, p, 16);
@@ -1426,10 +1441,7 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, const uint64_t* ltai
     w[j] = 0;
     if ((uint32_t)j < nw) __builtin_memcpy(&w[j], rp + 8 * j, 8);
   }
-  uint64_t last = 0;
-#pragma unroll
-  for (int b = 0; b < 7; ++b)
-    if ((uint32_t)b < nb) last |= (uint64_t)rp[8 * nw + b] << (8 * b);
+  const uint64_t last = nb ? load_partial_word(rp + 8 * nw, nb) : 0;
 #pragma unroll
   for (int j = 0; j < 15; ++j)
     if ((uint32_t)j < nw) {
@@ -1468,18 +1480,9 @@ __device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* lf
   uint64_t F[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) F[t] = 0;
-  if (valid && (uint64_t)q < N) {
-    uint64_t z0[K], z1[K];
-    ehc2<WIDTH, B>(str + q * XB + 16 * r, uniform_keys(a.ent + Ly::ehc), z0, z1);
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const uint64_t* kf = lfin0 + (t * (kFan - 1) + q) * B;
-      F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
-      F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
-    }
-  }
   // tail words m0 .. m0 + R - 1 (R <= XB / 8 <= 6 * 32), the last one
-  // zero-padded, loaded to its last byte only
+  // zero-padded, loaded to its last byte only; issued before the
+  // executions' loads, so that both are in flight together
   const uint64_t tb = N * XB, rem = L - tb;
   const uint64_t R = (rem + 7) / 8;
   uint64_t w[6];
@@ -1492,8 +1495,18 @@ __device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* lf
       if (8 * m + 8 <= rem) {
         __builtin_memcpy(&w[i], pw, 8);
       } else {
-        for (uint64_t b = 0; b < rem - 8 * m; ++b) w[i] |= (uint64_t)pw[b] << (8 * b);
+        w[i] = load_partial_word(pw, (uint32_t)(rem - 8 * m));
       }
+    }
+  }
+  if (valid && (uint64_t)q < N) {
+    uint64_t z0[K], z1[K];
+    ehc2<WIDTH, B>(str + q * XB + 16 * r, uniform_keys(a.ent + Ly::ehc), z0, z1);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const uint64_t* kf = lfin0 + (t * (kFan - 1) + q) * B;
+      F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
+      F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
     }
   }
 #pragma unroll
@@ -1572,13 +1585,15 @@ __global__ __launch_bounds__(64) void tiny_kernel(MainArgs a) {
 }
 
 // Small strings (1 .. kSmallMax executions, listed by the planner), one per
-// half-wave: wave w takes the pairs w, w + grid, ... of the list.  The next
-// pair's list entries and metadata are loaded before the current pair is
-// hashed.
+// half-wave: wave w takes the pairs w, w + grid, ... of the list.  The list
+// entries of the pair two rounds ahead and the offset and length of the next
+// round's pair are loaded before the current pair is hashed, so a pair costs
+// one exposed memory round trip (its bytes) instead of three.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
   using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t nsmall = uniform(a.ctl[kCtlSmall]);
   // Toeplitz tail keys, length keys and the final keys of level 0, read at
   // lane-varying indices, in LDS (one copy per wave)
@@ -1592,26 +1607,28 @@ __global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
   __syncthreads();
   const uint32_t G = gridDim.x;
   const int half = threadIdx.x >> 5;
-  // entry of this half in pair k
-  auto meta = [&](uint64_t k, uint32_t& s, uint64_t& L, uint64_t& off) {
+  // this half's list entry of pair k
+  auto entry = [&](uint64_t k) -> uint32_t {
     const uint64_t idx = 2 * k + half;
-    s = idx < nsmall ? a.small_list[idx] : 0xFFFFFFFFu;
-    L = off = 0;
-    if (s != 0xFFFFFFFFu) {
-      L = a.lengths[s];
-      off = a.offsets[s];
-    }
+    return idx < nsmall ? a.small_list[idx] : kNone;
   };
   uint64_t k = blockIdx.x;
-  uint32_t s;
-  uint64_t L, off;
-  meta(k, s, L, off);
+  uint32_t s = entry(k), s1 = entry(k + G);
+  uint64_t L = 0, off = 0;
+  if (s != kNone) {
+    L = a.lengths[s];
+    off = a.offsets[s];
+  }
   for (; 2 * k < nsmall; k += G) {
-    uint32_t s1;
-    uint64_t L1, off1;
-    meta(k + G, s1, L1, off1);
-    small_half<WIDTH, B>(a, lfin0, ltail, s != 0xFFFFFFFFu, s, L, off);
+    const uint32_t s2 = entry(k + 2 * (uint64_t)G);
+    uint64_t L1 = 0, off1 = 0;
+    if (s1 != kNone) {
+      L1 = a.lengths[s1];
+      off1 = a.offsets[s1];
+    }
+    small_half<WIDTH, B>(a, lfin0, ltail, s != kNone, s, L, off);
     s = s1;
+    s1 = s2;
     L = L1;
     off = off1;
   }
@@ -1870,7 +1887,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           if (8 * m + 8 <= rem) {
             __builtin_memcpy(&tw[i], pw, 8);
           } else {
-            for (uint64_t b = 0; b < rem - 8 * m; ++b) tw[i] |= (uint64_t)pw[b] << (8 * b);
+            tw[i] = load_partial_word(pw, (uint32_t)(rem - 8 * m));
           }
         }
       }
@@ -2271,7 +2288,7 @@ __global__ __launch_bounds__(64) void stream_final_kernel(const uint64_t* __rest
     if (8 * m + 8 <= tail_len) {
       __builtin_memcpy(&w, tail + 8 * m, 8);
     } else {
-      for (uint32_t b = 0; b < tail_len - 8 * m; ++b) w |= (uint64_t)tail[8 * m + b] << (8 * b);
+      w = load_partial_word(tail + 8 * m, tail_len - 8 * m);
     }
 #pragma unroll
     for (int t = 0; t < K; ++t) F[t] = nh_acc(F[t], w, ent[Ly::tail + t + m]);
