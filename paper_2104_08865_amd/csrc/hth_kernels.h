@@ -31,10 +31,11 @@ constexpr int kPlanPre = kPlanSums + 2;
 // Tail-only strings (shorter than one EHC execution) get no task: they are
 // listed apart and hashed one string per lane, in chunks of kTinyChunk
 // strings; wave w of the tail-only kernel takes chunks w, w + grid, ...
-// Small strings (1 .. kSmallMax executions: no tree node is complete) get no
-// task either: listed apart, one per half-wave of the small-string kernel.
+// Small strings (1 .. kSmallMax executions: at most one complete tree node,
+// of level 1) get no task either: listed apart, one per half-wave of the
+// small-string kernel.
 constexpr int kTinyChunk = 64;
-constexpr uint32_t kSmallMax = 7;
+constexpr uint32_t kSmallMax = 8;
 // Plans of more planner blocks than this get two scan kernels between their
 // two steps (linear in the block count); smaller ones sum in the fill step.
 // The scan cuts the blocks into at most kScanGroups runs of at least

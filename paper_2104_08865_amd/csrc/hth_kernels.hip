@@ -91,13 +91,48 @@ __device__ __forceinline__ meta32_ptr smeta(const uint32_t* p) { return (meta32_
 // past the page of the bytes' allocation).  Byte-by-byte loads in a loop of
 // n iterations were waited for one after another.
 __device__ __forceinline__ uint64_t load_partial_word(const uint8_t* p, uint32_t n) {
-  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-  const uint64_t* w = reinterpret_cast<const uint64_t*>(a & ~(uintptr_t)7);
-  const uint32_t s = 8 * (uint32_t)(a & 7);
-  const uint64_t lo = w[0];
-  const uint64_t hi = (a & 7) + n > 8 ? w[1] : 0;
-  const uint64_t v = s ? (lo >> s) | (hi << (64 - s)) : lo;
+  const uint32_t s = (uint32_t)(reinterpret_cast<uintptr_t>(p) & 7);
+  const uint8_t* ab = p - s;  // (derived from p: the loads stay global loads)
+  uint64_t lo, hi = 0;
+  __builtin_memcpy(&lo, ab, 8);
+  if (s + n > 8) __builtin_memcpy(&hi, ab + 8, 8);
+  const uint64_t v = s ? (lo >> (8 * s)) | (hi << (64 - 8 * s)) : lo;
   return v & ((1ull << (8 * n)) - 1);
+}
+
+// A run of tail words loaded by one lane, at most one of them partial: the
+// loads of every word are issued first (issue_tail_word) and the partial one
+// is shifted into place afterwards (finish_tail_words), so that no wait for
+// it falls between the loads (a wait inside the loop of loads held up every
+// later load of the run).
+struct PartialWord {
+  int idx = -1;      // which word of the run is partial (-1: none)
+  uint32_t sh = 0;   // its byte offset from the aligned word below it
+  uint32_t n = 0;    // its bytes
+  uint64_t hi = 0;   // the aligned word after it (when it reaches in)
+};
+__device__ __forceinline__ void issue_tail_word(const uint8_t* pw, uint64_t avail, int i, uint64_t& w,
+                                                PartialWord& pp) {
+  if (avail >= 8) {
+    __builtin_memcpy(&w, pw, 8);
+  } else {
+    const uint32_t s = (uint32_t)(reinterpret_cast<uintptr_t>(pw) & 7);
+    const uint8_t* ab = pw - s;
+    __builtin_memcpy(&w, ab, 8);
+    if (s + avail > 8) __builtin_memcpy(&pp.hi, ab + 8, 8);
+    pp.idx = i;
+    pp.sh = s;
+    pp.n = (uint32_t)avail;
+  }
+}
+template <int NW>
+__device__ __forceinline__ void finish_tail_words(uint64_t (&w)[NW], const PartialWord& pp) {
+#pragma unroll
+  for (int i = 0; i < NW; ++i)
+    if (i == pp.idx) {
+      const uint64_t v = pp.sh ? (w[i] >> (8 * pp.sh)) | (pp.hi << (64 - 8 * pp.sh)) : w[i];
+      w[i] = v & ((1ull << (8 * pp.n)) - 1);
+    }
 }
 
 __device__ __forceinline__ uint4 load16(const uint8_t* p) {
@@ -1460,23 +1495,33 @@ __device__ __forceinline__ void tiny_one(const MainArgs& a, const uint64_t* ltai
   }
 }
 
-// A small string (1 .. kSmallMax executions) per half-wave: every execution
-// is a leftover item of level 0 (no tree node is complete, Eq. (3)), so lane
-// group q of the half hashes execution q (EHC of its instance pair, §3.3,
-// loaded directly) and adds the final NH of the item at level 0, position q
-// (§5.2); the half's lanes add the tail words (Toeplitz keys, §6.1) and the
-// length term, and a half-wave sum gives the output.  `valid` is false for a
-// half without a string.  Called by the whole wave.
+// A small string (1 .. kSmallMax executions, at most 15) per half-wave.  The half's
+// lane groups take the executions in rounds (lane group q: executions q, q +
+// QH, ..., QH lane groups per half), each hashing the EHC of its instance
+// pair (§3.3, loaded directly).  With 8 executions or more, executions 0 .. 7
+// form the one complete level-1 node (Eq. (3)): their terms (§3.2's variant:
+// NH against the level-0 key of their position, the 8th raw) are summed over
+// the node's 8 lane groups and the node goes to the final NH as the leftover
+// at level 1, position 0; every other execution is a leftover at level 0,
+// position i mod 8 (§5.2).  The half's lanes add the tail words (Toeplitz
+// keys, §6.1) and the length term, and a half-wave sum gives the output.
+// `valid` is false for a half without a string.  Called by the whole wave.
 template <int WIDTH, int B>
-__device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* lfin0, const uint64_t* ltail, bool valid,
-                                           uint32_t s, uint64_t L, uint64_t off) {
+__device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* ltree0, const uint64_t* lfin0,
+                                           const uint64_t* lfin1, const uint64_t* ltail, bool valid, uint32_t s,
+                                           uint64_t L, uint64_t off) {
   using Ly = Layout<WIDTH, B>;
   constexpr int K = Family<WIDTH>::K;
   constexpr uint64_t XB = Ly::exec_bytes;
+  constexpr int LPB = Geo<B>::LPB;
+  constexpr int QH = 32 / LPB;                          // lane groups per half
+  constexpr int ROUNDS = ((int)kSmallMax + QH - 1) / QH;
+  static_assert(kSmallMax < 2 * kFan, "at most one complete level-1 node");
   const int l32 = threadIdx.x & 31;
-  const int q = l32 / Geo<B>::LPB, r = l32 % Geo<B>::LPB;
+  const int q = l32 / LPB, r = l32 % LPB;
   const uint8_t* __restrict__ str = a.bytes + off;
   const uint64_t N = L / XB;
+  const bool node = N >= (uint64_t)kFan;  // executions 0 .. 7 form a level-1 node
   uint64_t F[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) F[t] = 0;
@@ -1486,29 +1531,59 @@ __device__ __forceinline__ void small_half(const MainArgs& a, const uint64_t* lf
   const uint64_t tb = N * XB, rem = L - tb;
   const uint64_t R = (rem + 7) / 8;
   uint64_t w[6];
+  PartialWord pp;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const uint64_t m = (uint64_t)l32 + 32 * i;
     w[i] = 0;
-    if (valid && m < R) {
-      const uint8_t* pw = str + tb + 8 * m;
-      if (8 * m + 8 <= rem) {
-        __builtin_memcpy(&w[i], pw, 8);
+    if (valid && m < R) issue_tail_word(str + tb + 8 * m, rem - 8 * m, i, w[i], pp);
+  }
+#pragma unroll
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+    const int i = rd * QH + q;  // execution of this lane group
+    const int pos = i & 7;
+    uint64_t t0[K], t1[K];      // terms of the level-1 node's children
+#pragma unroll
+    for (int t = 0; t < K; ++t) t0[t] = t1[t] = 0;
+    if (valid && (uint64_t)i < N) {
+      uint64_t z0[K], z1[K];
+      ehc2<WIDTH, B>(str + (uint64_t)i * XB + 16 * r, uniform_keys(a.ent + Ly::ehc), z0, z1);
+      if (node && i < kFan) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          t0[t] = pos < kFan - 1 ? nh_acc(0, z0[t], ltree0[t * (kFan - 1) + pos]) : z0[t];
+          t1[t] = pos < kFan - 1 ? nh_acc(0, z1[t], ltree0[t * (kFan - 1) + pos]) : z1[t];
+        }
       } else {
-        w[i] = load_partial_word(pw, (uint32_t)(rem - 8 * m));
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t* kf = lfin0 + (t * (kFan - 1) + pos) * B;
+          F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
+          F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
+        }
+      }
+    }
+    if (rd == 0) {
+      // the node's 8 children are lane groups 0 .. 7 of the half's first
+      // round: sum them, then lane group 0 adds the node's final NH
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+#pragma unroll
+        for (int msk = LPB; msk < 8 * LPB; msk <<= 1) {
+          t0[t] += shfl_xor64(t0[t], msk);
+          t1[t] += shfl_xor64(t1[t], msk);
+        }
+      }
+      if (valid && node && q == 0) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          F[t] = nh_acc(F[t], t0[t], lfin1[t * B + 2 * r]);
+          F[t] = nh_acc(F[t], t1[t], lfin1[t * B + 2 * r + 1]);
+        }
       }
     }
   }
-  if (valid && (uint64_t)q < N) {
-    uint64_t z0[K], z1[K];
-    ehc2<WIDTH, B>(str + q * XB + 16 * r, uniform_keys(a.ent + Ly::ehc), z0, z1);
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const uint64_t* kf = lfin0 + (t * (kFan - 1) + q) * B;
-      F[t] = nh_acc(F[t], z0[t], kf[2 * r]);
-      F[t] = nh_acc(F[t], z1[t], kf[2 * r + 1]);
-    }
-  }
+  finish_tail_words(w, pp);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const uint64_t m = (uint64_t)l32 + 32 * i;
@@ -1599,11 +1674,17 @@ __global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
   // lane-varying indices, in LDS (one copy per wave)
   constexpr int NTAIL = (int)(Ly::len + K - Ly::tail);
   __shared__ uint64_t ltail[NTAIL];
-  __shared__ uint64_t lfin0[K * (kFan - 1) * B];
+  __shared__ uint64_t ltree0[K * (kFan - 1)];    // tree keys of level 0
+  __shared__ uint64_t lfin0[K * (kFan - 1) * B];  // final keys of level 0
+  __shared__ uint64_t lfin1[K * B];               // final keys of level 1, position 0
   if ((uint64_t)blockIdx.x * 2 >= nsmall) return;  // no pair for this wave
   for (int i = threadIdx.x; i < NTAIL; i += 64) ltail[i] = a.ent[Ly::tail + i];
+  for (int i = threadIdx.x; i < K * (kFan - 1); i += 64)
+    ltree0[i] = a.ent[Ly::tree + (i / (kFan - 1)) * kLevels * (kFan - 1) + i % (kFan - 1)];
   for (int i = threadIdx.x; i < K * (kFan - 1) * B; i += 64)
     lfin0[i] = a.ent[Ly::fin + (i / ((kFan - 1) * B)) * kLevels * (kFan - 1) * B + i % ((kFan - 1) * B)];
+  for (int i = threadIdx.x; i < K * B; i += 64)
+    lfin1[i] = a.ent[Ly::fin + (i / B) * kLevels * (kFan - 1) * B + (kFan - 1) * B + i % B];
   __syncthreads();
   const uint32_t G = gridDim.x;
   const int half = threadIdx.x >> 5;
@@ -1626,7 +1707,7 @@ __global__ __launch_bounds__(64) void small_kernel(MainArgs a) {
       L1 = a.lengths[s1];
       off1 = a.offsets[s1];
     }
-    small_half<WIDTH, B>(a, lfin0, ltail, s != kNone, s, L, off);
+    small_half<WIDTH, B>(a, ltree0, lfin0, lfin1, ltail, s != kNone, s, L, off);
     s = s1;
     s1 = s2;
     L = L1;
@@ -1876,20 +1957,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     // region's bytes have arrived, so that waiting for them never holds up a
     // region).
     uint64_t tw[3];
+    PartialWord tpp;
     auto load_tail = [&]() {
       const uint64_t tb = N * XB, rem = L - tb, R = (rem + 7) / 8;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const uint64_t m = (uint64_t)lane + 64 * i;
         tw[i] = 0;
-        if (m < R) {
-          const uint8_t* pw = str + tb + 8 * m;
-          if (8 * m + 8 <= rem) {
-            __builtin_memcpy(&tw[i], pw, 8);
-          } else {
-            tw[i] = load_partial_word(pw, (uint32_t)(rem - 8 * m));
-          }
-        }
+        if (m < R) issue_tail_word(str + tb + 8 * m, rem - 8 * m, i, tw[i], tpp);
       }
     };
 
@@ -1906,6 +1981,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         stage_issue<WIDTH, B>(task_next_region<WIDTH, B>(tn), 0, stage);
         load_tail();
       }
+      finish_tail_words(tw, tpp);
       const uint64_t R = (L - N * XB + 7) / 8;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -2018,6 +2094,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       if (tau == ntask - 1) {
         // tail (§6.1): words m0 .. m0+R-1, output t keyed by S_tail[t + m]
         if (!tail_loaded) load_tail();
+        finish_tail_words(tw, tpp);
         const uint64_t R = (L - N * XB + 7) / 8;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {

@@ -76,6 +76,19 @@ def test_b4_tree_boundaries(env, width):
     _check(env, data, offs, lens, width, "tree boundaries")
 
 
+@pytest.mark.parametrize("width", WIDTHS)
+def test_b4_small_strings_around_one_node(env, width):
+    """Strings of 1 .. 17 executions of the b = 4 family (the small-string
+    kernel's, the one-node case of 8, the first task strings), tails of 0, 1,
+    7 and almost an execution, at offsets 0 .. 7 mod 8."""
+    xb = xb4(width)
+    lens = np.array([n * xb + extra for n in range(1, 18) for extra in (0, 1, 7, xb - 1)], dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    offs = offs + np.arange(lens.size, dtype=np.uint64) % np.uint64(8)
+    data = wl.random_bytes(36, total + 8)
+    _check(env, data, offs, lens, width, "1-17 executions")
+
+
 @pytest.mark.parametrize("level", [0, 1, 2])
 def test_b4_forced_task_levels(env, level):
     """Tasks of 256 * 8^level executions: level 0 merges levels 3 and up

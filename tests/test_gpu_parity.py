@@ -83,6 +83,20 @@ def test_tree_boundaries(env, width):
     _check(env, data, offs, lens, width, "tree boundaries")
 
 
+@pytest.mark.parametrize("width", WIDTHS)
+def test_small_strings_around_one_node(env, width):
+    """Strings of 1 .. 17 executions (the small-string kernel's strings,
+    among them the one-node case of exactly 8, and the first ones hashed as
+    tasks), each with no tail, a one-byte tail and an almost full one, at
+    unaligned addresses (offsets 0 .. 7 mod 8)."""
+    xb = wl.execution_bytes(width)
+    lens = np.array([n * xb + extra for n in range(1, 18) for extra in (0, 1, 7, xb - 1)], dtype=np.uint64)
+    offs, total = wl.pack(lens)
+    offs = offs + np.arange(lens.size, dtype=np.uint64) % np.uint64(8)
+    data = wl.random_bytes(16, total + 8)
+    _check(env, data, offs, lens, width, "1-17 executions")
+
+
 @pytest.mark.parametrize("level", [0, 1, 2])
 def test_forced_task_levels_same_result(env, level):
     """Every task size gives the oracle's values: level 0 merges every level
