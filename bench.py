@@ -147,6 +147,8 @@ def run_main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default line")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg of the default line")
     ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default launch choice")
+    ap.add_argument("--uneven-subsets", action="store_true",
+                    help="uneven workload: also hash subsets of the batch by execution count, each alone")
     ap.add_argument("--block-words", type=int, default=8, choices=(4, 8),
                     help="throughput workload: the family's block size b (8, or 4 for the 256-bit family)")
     ap.add_argument("--no-per-string", action="store_true",
@@ -533,6 +535,8 @@ def uneven_leg(args, autotune=False, per_string=UNEVEN_PER_STRING_SAMPLE):
                          f"single thread pinned to core {core}",
                "seconds": dt, "bit_exact_vs_gpu": bool((ref == persistent[idx]).all())}
         log(f"[bench] uneven cpu oracle: {idx.size} strings in {dt:.1f} s, exact={cpu['bit_exact_vs_gpu']}")
+    subsets = _uneven_subsets(hth, torch, seed, data, o, n, lens, width) if getattr(args, "uneven_subsets", False) \
+        else None
     del data, out, g
     torch.cuda.empty_cache()
 
@@ -556,8 +560,37 @@ def uneven_leg(args, autotune=False, per_string=UNEVEN_PER_STRING_SAMPLE):
         "persistent_over_per_string": persistent_gbps / per_gbps if per_gbps else None,
         "all_identical": agree,
         "autotune_ms": {f"{c[0]}/{c[1]}-{c[2]}": round(t, 4) for c, t in times.items()},
+        "subsets": subsets,
         "cpu_baseline": cpu,
     }
+
+
+UNEVEN_SUBSETS = (("shorter than one execution (tail only)", 0, 0), ("1-8 executions", 1, 8),
+                  ("9-16 executions", 9, 16), ("17-63 executions", 17, 63), ("1-63 executions", 1, 63),
+                  ("64-127 executions", 64, 127), (">= 128 executions", 128, None), ("all", 0, None))
+
+
+def _uneven_subsets(hth, torch, seed, data, o, n, lens, width):
+    """The uneven batch's strings grouped by execution count, each group
+    hashed alone (its offsets and lengths in one call): median of 8 calls of
+    HIP events around the hashing, tail-only and small-string kernels."""
+    from paper_2104_08865_amd import workloads as wl
+    N = lens // wl.execution_bytes(width)
+    timer = hth.Timer()
+    rows = []
+    for label, lo, hi in UNEVEN_SUBSETS:
+        sel = (N >= lo) & (N <= hi if hi is not None else True)
+        idx = torch.from_numpy(np.nonzero(sel)[0]).to(o.device)
+        so, sn = o[idx].contiguous(), n[idx].contiguous()
+        ms = []
+        for _ in range(10):
+            hth.hash_batch(seed, data, so, sn, width, timer=timer)
+            ms.append(timer.elapsed_ms())
+        m = float(np.median(ms[2:]))
+        b = int(lens[sel].sum())
+        rows.append({"subset": label, "strings": int(sel.sum()), "bytes": b, "ms": m, "GBps": b / m / 1e6})
+        log(f"[bench] uneven subset {label}: {int(sel.sum())} strings, {m:.4f} ms, {b / m / 1e6:.0f} GB/s")
+    return rows
 
 
 def _per_string(hth, torch, seed, data, o, n, width, idx, dev):
@@ -597,6 +630,7 @@ def _uneven_line(args, leg):
         "persistent_over_per_string": leg["persistent_over_per_string"],
         "all_three_identical": leg["all_identical"],
         "autotune_ms": leg["autotune_ms"],
+        **({"subsets": leg["subsets"]} if leg.get("subsets") else {}),
         "cpu_baseline": leg["cpu_baseline"],
     }
 
