@@ -303,7 +303,7 @@ def run_throughput(args):
 
 SERVE_LOADS = (0.25, 0.5, 0.8)
 SERVE_CLIENTS = 4  # replay threads of the staged submits (their copies into the staging overlap)
-SERVE_PINNED_CLIENTS = 1  # replay thread of the pinned submits (no copy; one receiving thread)
+SERVE_PINNED_CLIENTS = 4  # replay threads of the pinned submits (no copy)
 
 
 def serve_legs(n_req, verify=False):

@@ -414,9 +414,9 @@ hth_status hth_serve_wait_many(hth_server *server, const uint64_t *tickets, uint
 /* Load replay: submits request i (bytes base + offsets[i], lengths[i],
    width widths[i]) at arrival_ns[i] nanoseconds after the call starts,
    retrying while the server answers HTH_E_BUSY; tickets go to tickets[i].
-   `threads` client threads (1..64) share the requests round robin (request
-   i goes to thread i mod threads, each in arrival order), so copies into the
-   staging overlap.  Returns after the last submit, not after completion;
+   `threads` client threads (1..64) share the requests in chunks of 64
+   consecutive ones (chunk c goes to thread c mod threads; each thread
+   submits in request order), so copies into the staging overlap.  Returns after the last submit, not after completion;
    on an error other than BUSY the remaining requests are not submitted. */
 hth_status hth_serve_replay(hth_server *server, const uint8_t *base, const uint64_t *offsets,
                             const uint64_t *lengths, const uint32_t *widths, const uint64_t *arrival_ns,

@@ -126,11 +126,36 @@ struct Inflight {
 
 enum : uint8_t { kFree = 0, kPending = 1, kReady = 2 };
 
+// A ticket's slot.  Only the submitter that finds it free moves it to
+// pending (the ticket numbers of outstanding requests differ modulo the table
+// size), the batch's slot thread to ready (under r_mu) and the collector back
+// to free (under r_mu): the state is atomic so that submitters need no lock
+// of the ticket table.
 struct Entry {
-  uint64_t ticket = 0;
-  uint8_t state = kFree;
+  std::atomic<uint64_t> ticket{0};
+  std::atomic<uint8_t> state{kFree};
   uint8_t width = 0;
   uint8_t out[40];
+};
+
+// The queue's lock: its holders work for a few hundred nanoseconds (a
+// submit) or microseconds (an admission), and several submitting threads
+// contend for it, where a sleeping mutex queued them through the kernel on
+// every conflict.  Spins briefly, then yields.
+class SpinMutex {
+ public:
+  void lock() {
+    for (int n = 0; flag_.exchange(true, std::memory_order_acquire); ++n) {
+      while (flag_.load(std::memory_order_relaxed)) {
+        if (++n > 64) std::this_thread::yield();
+      }
+    }
+  }
+  bool try_lock() { return !flag_.exchange(true, std::memory_order_acquire); }
+  void unlock() { flag_.store(false, std::memory_order_release); }
+
+ private:
+  std::atomic<bool> flag_{false};
 };
 
 }  // namespace
@@ -148,8 +173,8 @@ struct hth_server {
   // and the batches in flight (admission order), all under q_mu; a
   // request's bytes are copied outside the lock, so a slot admits a request
   // only once its `copied` flag is set
-  std::mutex q_mu;
-  std::condition_variable q_cv;
+  SpinMutex q_mu;
+  std::condition_variable_any q_cv;
   Ring host;
   Ring dev;
   std::deque<Request> pending;
@@ -162,14 +187,15 @@ struct hth_server {
   // tickets
   std::mutex r_mu;
   std::condition_variable r_cv;
-  std::vector<Entry> entries;
+  std::unique_ptr<Entry[]> entries;
   uint64_t mask = 0;
 
-  // statistics since the last reset (under r_mu)
+  // statistics since the last reset: completions under r_mu, submissions
+  // under q_mu or atomic
   std::vector<float> lat_us;
-  uint64_t n_submitted = 0, n_completed = 0, n_deferred = 0, n_busy = 0, n_batches = 0, n_batch_reqs = 0,
-           n_bytes = 0;
-  bool have_first = false;
+  uint64_t n_completed = 0, n_batches = 0, n_batch_reqs = 0, n_bytes = 0;
+  std::atomic<uint64_t> n_submitted{0}, n_deferred{0}, n_busy{0};
+  bool have_first = false;  // (under q_mu)
   Clock::time_point t_first, t_last;
 
   std::atomic<bool> stop{false};
@@ -210,7 +236,6 @@ bool admit_locked(hth_server* s, Slot& sl) {
       // device budget exhausted: the request waits for a batch to retire
       if (!r.deferred) {
         r.deferred = true;
-        std::lock_guard<std::mutex> rl(s->r_mu);
         ++s->n_deferred;
       }
       break;
@@ -342,7 +367,7 @@ void retire(hth_server* s, Slot& sl) {
       Entry& en = s->entries[r.ticket & s->mask];
       std::memcpy(en.out, sl.h_out + sl.out_at[w] + fillw[w] * r.width, r.width);
       ++fillw[w];
-      en.state = kReady;
+      en.state.store(kReady, std::memory_order_release);
       s->lat_us.push_back((float)std::chrono::duration<double, std::micro>(now - r.t_submit).count());
       bytes += r.len;
     }
@@ -354,7 +379,7 @@ void retire(hth_server* s, Slot& sl) {
     s->r_cv.notify_all();
   }
   {
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    std::lock_guard<SpinMutex> lk(s->q_mu);
     for (Inflight& f : s->inflight)
       if (f.seq == sl.seq) f.done = true;
     while (!s->inflight.empty() && s->inflight.front().done) {
@@ -378,7 +403,7 @@ void worker_main(hth_server* s, uint32_t si) {
   for (;;) {
     bool got = false;
     {
-      std::unique_lock<std::mutex> lk(s->q_mu);
+      std::unique_lock<SpinMutex> lk(s->q_mu);
       // counted idle before looking at the queue: a submit that the look
       // misses sees the count and wakes a slot (both are sequentially
       // consistent atomics)
@@ -447,18 +472,18 @@ void prefault(uint8_t* p, uint64_t n) {
 hth_status take(hth_server* s, uint64_t ticket, uint8_t* out, bool block) {
   std::unique_lock<std::mutex> lk(s->r_mu);
   Entry& en = s->entries[ticket & s->mask];
-  if (en.ticket != ticket || en.state == kFree)
+  if (en.ticket.load() != ticket || en.state.load() == kFree)
     return fail(HTH_E_INVALID, "ticket %llu is unknown or already collected", (unsigned long long)ticket);
-  if (en.state == kPending) {
+  if (en.state.load() == kPending) {
     if (!block) {
       if (s->failed.load()) return server_error(s);
       return HTH_E_BUSY;
     }
-    s->r_cv.wait(lk, [&] { return en.state == kReady || s->failed.load(); });
-    if (en.state != kReady) return server_error(s);
+    s->r_cv.wait(lk, [&] { return en.state.load() == kReady || s->failed.load(); });
+    if (en.state.load() != kReady) return server_error(s);
   }
   std::memcpy(out, en.out, en.width);
-  en.state = kFree;
+  en.state.store(kFree, std::memory_order_release);
   return HTH_OK;
 }
 
@@ -477,32 +502,23 @@ hth_status submit(hth_server* s, const void* host_bytes, uint64_t len, uint32_t 
   if (s->failed.load()) return server_error(s);
   uint64_t t = 0, pos = 0;
   {
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    std::lock_guard<SpinMutex> lk(s->q_mu);
     t = s->next_ticket;
-    const uint64_t old_head = s->host.head, old_tail = s->host.tail;
-    bool ok = pinned || s->host.alloc(pad(len), &pos);
-    if (ok) {
-      std::lock_guard<std::mutex> rl(s->r_mu);
-      Entry& en = s->entries[t & s->mask];
-      if (en.state != kFree) {
-        ok = false;
-        s->host.head = old_head;  // undo: nothing was allocated after it
-        s->host.tail = old_tail;
-      } else {
-        en.ticket = t;
-        en.state = kPending;
-        en.width = (uint8_t)out_width;
-        ++s->n_submitted;
-        if (!s->have_first) {
-          s->have_first = true;
-          s->t_first = t0;
-        }
-      }
-    }
+    Entry& en = s->entries[t & s->mask];
+    // (a free slot was freed by its collector with a release store: its
+    // previous ticket's result has been read)
+    bool ok = en.state.load(std::memory_order_acquire) == kFree && (pinned || s->host.alloc(pad(len), &pos));
     if (!ok) {
-      std::lock_guard<std::mutex> rl(s->r_mu);
       ++s->n_busy;
       return HTH_E_BUSY;
+    }
+    en.ticket.store(t);
+    en.width = (uint8_t)out_width;
+    en.state.store(kPending, std::memory_order_release);
+    ++s->n_submitted;
+    if (!s->have_first) {
+      s->have_first = true;
+      s->t_first = t0;
     }
     ++s->next_ticket;
     s->copied[t & s->mask].store(pinned ? 1 : 0);
@@ -516,7 +532,7 @@ hth_status submit(hth_server* s, const void* host_bytes, uint64_t len, uint32_t 
   s->copied[t & s->mask].store(1);
   if (s->idle_slots.load()) {
     // the lock orders the notify after an idle slot's look at the queue
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    std::lock_guard<SpinMutex> lk(s->q_mu);
     s->q_cv.notify_one();
   }
   return HTH_OK;
@@ -533,9 +549,14 @@ hth_status replay(hth_server* s, const uint8_t* base, const uint64_t* offsets, c
   std::atomic<int> first_err{HTH_OK};
   std::string err_msg;
   std::mutex err_mu;
-  // client k submits requests k, k + threads, ... at their arrival times
+  // client k submits the chunks k, k + threads, ... of kReplayChunk
+  // consecutive requests, each request at its arrival time (a client's
+  // requests are neighbours in memory, as a client filling its own buffer
+  // would make them, so pinned ones go to the device in few copies)
+  constexpr uint64_t kReplayChunk = 64;
   auto client = [&](uint32_t k) {
-    for (uint64_t i = k; i < n && first_err.load() == HTH_OK; i += threads) {
+    for (uint64_t i = (uint64_t)k * kReplayChunk; i < n && first_err.load() == HTH_OK;
+         i = (i + 1) % kReplayChunk ? i + 1 : i + 1 + (uint64_t)(threads - 1) * kReplayChunk) {
       const Clock::time_point due = t0 + std::chrono::nanoseconds(arrival_ns[i]);
       while (Clock::now() < due) {
       }
@@ -614,7 +635,7 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
   s->dev.cap = c.max_device_bytes;
   s->mask = outstanding - 1;
   try {
-    s->entries.resize(outstanding);
+    s->entries.reset(new Entry[outstanding]);
     s->slots.resize(c.slots);
     s->copied.reset(new std::atomic<uint8_t>[outstanding]);
     for (uint32_t i = 0; i < outstanding; ++i) s->copied[i].store(0);
@@ -657,7 +678,7 @@ hth_status hth_serve_create(const hth_serve_config* config, const hth_seed* seed
     for (uint32_t i = 0; i < c.slots; ++i) s->workers.emplace_back(worker_main, s, i);
   } catch (...) {
     {
-      std::lock_guard<std::mutex> lk(s->q_mu);
+      std::lock_guard<SpinMutex> lk(s->q_mu);
       s->stop.store(true);
     }
     s->q_cv.notify_all();
@@ -715,7 +736,7 @@ hth_status hth_serve_replay_pinned(hth_server* s, const uint8_t* base, const uin
 hth_status hth_serve_pause(hth_server* s, int32_t paused) {
   if (!s) return fail(HTH_E_INVALID, "hth_serve_pause: null server");
   {
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    std::lock_guard<SpinMutex> lk(s->q_mu);
     s->paused.store(paused != 0);
   }
   s->q_cv.notify_all();
@@ -727,6 +748,7 @@ hth_status hth_serve_stats(hth_server* s, hth_serve_report* out) {
   std::vector<float> lat;
   hth_serve_report r{};
   {
+    std::lock_guard<SpinMutex> ql(s->q_mu);
     std::lock_guard<std::mutex> lk(s->r_mu);
     lat = s->lat_us;
     r.submitted = s->n_submitted;
@@ -764,9 +786,11 @@ hth_status hth_serve_stats(hth_server* s, hth_serve_report* out) {
 
 hth_status hth_serve_reset_stats(hth_server* s) {
   if (!s) return fail(HTH_E_INVALID, "hth_serve_reset_stats: null server");
+  std::lock_guard<SpinMutex> ql(s->q_mu);
   std::lock_guard<std::mutex> lk(s->r_mu);
   s->lat_us.clear();
-  s->n_submitted = s->n_completed = s->n_deferred = s->n_busy = s->n_batches = s->n_batch_reqs = s->n_bytes = 0;
+  s->n_completed = s->n_batches = s->n_batch_reqs = s->n_bytes = 0;
+  s->n_submitted = s->n_deferred = s->n_busy = 0;
   s->have_first = false;
   return HTH_OK;
 }
@@ -774,7 +798,7 @@ hth_status hth_serve_reset_stats(hth_server* s) {
 hth_status hth_serve_destroy(hth_server* s) {
   if (!s) return HTH_OK;
   {
-    std::lock_guard<std::mutex> lk(s->q_mu);
+    std::lock_guard<SpinMutex> lk(s->q_mu);
     s->stop.store(true);
   }
   s->q_cv.notify_all();
