@@ -686,11 +686,18 @@ __device__ void plan_fill_body(
   const uint64_t unit = texec * exec_bytes + kTaskOverheadBytes;  // work of a full task
   uint32_t nlead = 0;
   for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
-    int lo = 0, hi = nstr - 1;  // first string whose inclusive count exceeds e
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if ((uint64_t)incl[mid] > e) hi = mid;
-      else lo = mid + 1;
+    // first string whose inclusive count exceeds e: the guess from the
+    // average tasks per string (exact when the block's strings have equal
+    // task counts), else a binary search
+    int lo = (int)(e * (uint64_t)nstr / blk_t);
+    if (!((uint64_t)incl[lo] > e && (lo == 0 || (uint64_t)incl[lo - 1] <= e))) {
+      lo = 0;
+      int hi = nstr - 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((uint64_t)incl[mid] > e) hi = mid;
+        else lo = mid + 1;
+      }
     }
     const uint64_t task = task_base + e;
     const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
