@@ -41,3 +41,24 @@ def test_traffic_only_for_the_code_it_was_taken_on(tmp_path):
     # the committed summaries match the committed kernel code
     assert bench.measured_traffic(24) is not None
     assert bench.measured_traffic(24, bench.UNEVEN_TRAFFIC_FILE) is not None
+
+
+def test_uneven_subsets_partition_the_batch():
+    """The uneven batch's per-subset rows: the disjoint groups (tail only,
+    1-8, 9-16, 17-63, 64-127, >= 128 executions) cover every string once,
+    1-63 is the union of its three groups, and 'all' is the whole batch."""
+    import numpy as np
+    from paper_2104_08865_amd import workloads as wl
+    lens = wl.uneven_lengths(3)
+    N = lens // wl.execution_bytes(24)
+    rows = {label: (N >= lo) & (N <= hi if hi is not None else True) for label, lo, hi in bench.UNEVEN_SUBSETS}
+    disjoint = ["shorter than one execution (tail only)", "1-8 executions", "9-16 executions", "17-63 executions",
+                "64-127 executions", ">= 128 executions"]
+    count = np.zeros(lens.size, dtype=np.int64)
+    for label in disjoint:
+        count += rows[label]
+    assert (count == 1).all()
+    assert (rows["1-63 executions"] == (rows["1-8 executions"] | rows["9-16 executions"] |
+                                        rows["17-63 executions"])).all()
+    assert rows["all"].all()
+    assert rows["shorter than one execution (tail only)"].sum() == (lens < wl.execution_bytes(24)).sum()
