@@ -681,6 +681,26 @@ def run_long(args):
             same &= bool((h.cpu().numpy() == whole).all())
         streaming[f"{piece >> 20} MiB pieces"] = {"GBps": max(rates), "same_value_as_batch": same}
         log(f"[bench] streaming in {piece >> 20} MiB pieces: {max(rates):.0f} GB/s, same value={same}")
+    # the same 128 MiB pieces through gathered updates: `per` pieces a call
+    # (the library hashes the blocks of a call's pieces in one launch per
+    # group of up to 64 pieces and 1024 blocks)
+    piece = 128 << 20
+    views = [data[at:at + piece] for at in range(0, sz, piece)]
+    for per in (8, len(views)):
+        rates, same = [], True
+        for rep in range(3):
+            st.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in range(0, len(views), per):
+                st.update_gather(views[c:c + per])
+            h = st.final()
+            torch.cuda.synchronize()
+            rates.append(sz / (time.perf_counter() - t0) / 1e9)
+            same &= bool((h.cpu().numpy() == whole).all())
+        key = f"{piece >> 20} MiB pieces, {per} per gathered call"
+        streaming[key] = {"GBps": max(rates), "same_value_as_batch": same}
+        log(f"[bench] streaming in {key}: {max(rates):.0f} GB/s, same value={same}")
     st.free()
     cpu = None
     if not args.no_cpu_baseline:

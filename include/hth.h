@@ -287,7 +287,7 @@ hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t mi
 typedef struct hth_stream hth_stream;
 
 /* Create an empty stream for `seed` (its family) and out_width.  Allocates
-   its device state (about 100 KB) and a planning workspace; synchronous.
+   its device state (about 400 KB) and a planning workspace; synchronous.
    The seed must outlive the stream.  Errors: HTH_E_INVALID (null pointer,
    bad out_width, seed on another device), HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_stream **out);
@@ -297,6 +297,22 @@ hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_strea
    call on one hth_stream must be ordered (the same HIP stream, or
    synchronised).  len == 0 is a no-op.  Errors: HTH_E_INVALID, HTH_E_HIP. */
 hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len, hipStream_t stream);
+
+/* Append `count` pieces in order: the same state as `count` calls of
+   hth_stream_update, with the blocks of up to 64 pieces hashed in one
+   launch (fewer when their block tables pass 1024 entries; the executions
+   that straddle two pieces are assembled in the stream's state and hashed in
+   the same launch).  A piece of a few hundred MB leaves most of the device
+   idle on its own (the tree of Eq. (3) is cut into aligned blocks of 8^L
+   executions, each hashed by whole passes of 128 executions, 256 for b = 4);
+   gathered, the pieces fill it together.  pieces[i] is a device pointer to lens[i] bytes
+   (any alignment; lens[i] == 0 is skipped), the pieces may lie in different
+   allocations; both host arrays are read during the call, the bytes by the
+   work enqueued on `stream` (valid until it completes).  Same ordering rule
+   as hth_stream_update.  Errors: HTH_E_INVALID (null stream, null arrays
+   with count > 0, null piece of non-zero length), HTH_E_HIP. */
+hth_status hth_stream_update_gather(hth_stream *st, const uint8_t *const *pieces, const uint64_t *lens,
+                                    uint32_t count, hipStream_t stream);
 
 /* Write the out_width-byte hash of everything appended so far to device
    pointer `out` (enqueued on `stream`).  The stream is unchanged and can

@@ -155,6 +155,80 @@ hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* en
 // The block table of one update (device arrays), as the host plans it.
 hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
                                uint32_t* lev, hipStream_t stream);
+
+// Gathered update: a group of pieces appended with one root-mode launch.
+// Segment 0 is the carried bytes, segments 1 .. nseg-1 the pieces; their
+// concatenation is cut into full executions.
+constexpr int kGatherMax = 64;             // pieces per group
+constexpr uint32_t kStreamTable = 1024;    // table entries per launch (one planner workgroup)
+constexpr int kStreamLevels = 20;          // levels of the stack
+struct GatherArgs {
+  uint64_t e0;                             // executions absorbed before the group
+  uint32_t xb, nseg;
+  const uint8_t* seg[kGatherMax + 1];
+  uint64_t seg_len[kGatherMax + 1];
+  const uint8_t* base;                     // table offsets are relative to this
+  uint8_t* joins;                          // [kGatherMax][xb] executions that straddle segments
+  uint8_t* carry;                          // segment 0; rewritten with the group's trailing bytes
+  uint64_t* off;
+  uint64_t* len;
+  uint32_t* lev;
+  // The host's walk (GatherWalk) before segment k = 1 .. nseg-1 and after
+  // the last (k = nseg): the segment's start in the concatenation (w_at[0]
+  // = 0, w_at[nseg] = the total), the next execution not yet emitted, the
+  // joins so far and the table index of the segment's first entry; then the
+  // group's joins and full executions.
+  uint64_t w_at[kGatherMax + 2];
+  uint64_t w_next[kGatherMax + 2];
+  uint32_t w_nj[kGatherMax + 2];
+  uint32_t w_first[kGatherMax + 2];
+  uint32_t nj;
+  uint64_t nfull;
+};
+static_assert(sizeof(GatherArgs) <= 4096, "a kernel argument");
+
+// The full executions of a group's concatenation, in order, one segment at
+// a time: block(x, L, at) for each maximal aligned block of 8^L executions
+// lying inside one piece (x: index of its first execution, at: its first
+// byte), join(j, s) for the j-th execution that straddles segments (s: its
+// offset in the concatenation; at most one per segment boundary).  The host
+// counts a group's table with it and the table kernel writes the table with
+// it, so the two cannot disagree.
+struct GatherWalk {
+  uint64_t xb, e0;
+  uint64_t at = 0, next = 0;  // segment start in the concatenation; next execution not yet emitted
+  uint32_t nj = 0;
+  __host__ __device__ GatherWalk(uint64_t xb_, uint64_t e0_, uint64_t carry_len) : xb(xb_), e0(e0_), at(carry_len) {}
+  __host__ __device__ GatherWalk(uint64_t xb_, uint64_t e0_, uint64_t at_, uint64_t next_, uint32_t nj_)
+      : xb(xb_), e0(e0_), at(at_), next(next_), nj(nj_) {}
+  template <class Block, class Join>
+  __host__ __device__ void piece(const uint8_t* p, uint64_t len, Block&& block, Join&& join) {
+    const uint64_t a = (at + xb - 1) / xb, b = (at + len) / xb;  // executions inside the piece
+    if (b > a) {
+      for (; next < a; ++next) join(nj++, next * xb);
+      for (uint64_t x = e0 + a, end = e0 + b; x < end;) {
+        int L = 0;  // (powers of 8: masks and shifts, no 64-bit division)
+        while (L + 1 < kStreamLevels && (x & ((1ull << (3 * (L + 1))) - 1)) == 0 && end - x >= (1ull << (3 * (L + 1))))
+          ++L;
+        block(x, L, p + ((x - e0) * xb - at));
+        x += 1ull << (3 * L);
+      }
+      next = b;
+    }
+    at += len;
+  }
+  // The joins after the last piece's blocks; returns the full executions.
+  template <class Join>
+  __host__ __device__ uint64_t finish(Join&& join) {
+    const uint64_t nfull = at / xb;
+    for (; next < nfull; ++next) join(nj++, next * xb);
+    return nfull;
+  }
+};
+
+// Writes the table of a group (blocks and joins in order), assembles the
+// joins and rewrites the carried bytes.
+hipError_t launch_stream_gather(const GatherArgs& g, hipStream_t stream);
 hipError_t launch_stream_final(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* stack,
                                const uint32_t* counts, const uint8_t* tail, uint32_t tail_len, uint64_t total_len,
                                uint8_t* out, hipStream_t stream);

@@ -326,6 +326,15 @@ __device__ __forceinline__ void plan_counts(uint64_t N, int j, uint32_t pass_log
   }
 }
 
+// The smallest multiple of d > 0 that is at least x, for x < 2^53 (sums of
+// string bytes): a double estimate of x / d, corrected exactly.
+__device__ __forceinline__ uint64_t round_up_to(uint64_t x, uint64_t d, double inv_d) {
+  uint64_t q = (uint64_t)((double)x * inv_d);
+  while (q > 0 && q * d > x) --q;  // q = floor(x / d)
+  while ((q + 1) * d <= x) ++q;
+  return q * d == x ? x : (q + 1) * d;
+}
+
 constexpr int kPlanThreads = 256;
 constexpr int kPlanPer = 4;
 constexpr int kPlanBlock = kPlanThreads * kPlanPer;
@@ -684,31 +693,48 @@ __device__ void plan_fill_body(
   const int nstr = (int)((count - first) < (uint64_t)kPlanBlock ? (count - first) : kPlanBlock);
   const uint64_t texec = 1ull << (pass_log2 + 3 * jsel);
   const uint64_t unit = texec * exec_bytes + kTaskOverheadBytes;  // work of a full task
+  // Each thread fills a contiguous run of the block's tasks: the string of
+  // its first task is found once, then only moves forward.
+  const uint64_t per = (blk_t + kPlanThreads - 1) / kPlanThreads;
+  const uint64_t e_lo = (uint64_t)tid * per < blk_t ? (uint64_t)tid * per : blk_t;
+  const uint64_t e_hi = e_lo + per < blk_t ? e_lo + per : blk_t;
+  const int tshift = (int)pass_log2 + 3 * jsel;  // log2 of a full task's executions
+  const double inv_bucket = 1.0 / (double)bucket;
   uint32_t nlead = 0;
-  for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
-    // first string whose inclusive count exceeds e: the guess from the
+  uint64_t leads = 0;  // lead flags of this thread's first 64 tasks (bit k: task e_lo + k)
+  if (e_lo < e_hi) {
+    // first string whose inclusive count exceeds e_lo: the guess from the
     // average tasks per string (exact when the block's strings have equal
     // task counts), else a binary search
-    int lo = (int)(e * (uint64_t)nstr / blk_t);
-    if (!((uint64_t)incl[lo] > e && (lo == 0 || (uint64_t)incl[lo - 1] <= e))) {
+    int lo = (int)(e_lo * (uint64_t)nstr / blk_t);
+    if (!((uint64_t)incl[lo] > e_lo && (lo == 0 || (uint64_t)incl[lo - 1] <= e_lo))) {
       lo = 0;
       int hi = nstr - 1;
       while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if ((uint64_t)incl[mid] > e) hi = mid;
+        if ((uint64_t)incl[mid] > e_lo) hi = mid;
         else lo = mid + 1;
       }
     }
-    const uint64_t task = task_base + e;
-    const uint64_t tau = e - (lo > 0 ? incl[lo - 1] : 0);
-    const uint64_t L = slen[lo];
-    uint64_t ntk, nac;
-    plan_counts(L / exec_bytes, jsel, pass_log2, ntk, nac);
-    const uint64_t w0 = wstart[lo] + tau * unit;
-    const uint64_t w1 = tau + 1 < ntk ? w0 + unit : wstart[lo] + L + kTaskOverheadBytes * ntk;
-    const bool lead = (w0 + bucket - 1) / bucket * bucket < w1;
-    task_string[task] = (uint32_t)(first + lo) | (lead ? 0x80000000u : 0u);
-    nlead += lead;
+    uint64_t before = lo > 0 ? incl[lo - 1] : 0;  // tasks of the block's strings before string lo
+    uint64_t L = slen[lo];
+    uint64_t ntk = (L / exec_bytes + (1ull << tshift) - 1) >> tshift;
+    for (uint64_t e = e_lo; e < e_hi; ++e) {
+      while ((uint64_t)incl[lo] <= e) {  // on to the next string with tasks
+        before = incl[lo];
+        ++lo;
+        L = slen[lo];
+        ntk = (L / exec_bytes + (1ull << tshift) - 1) >> tshift;
+      }
+      const uint64_t task = task_base + e;
+      const uint64_t tau = e - before;
+      const uint64_t w0 = wstart[lo] + tau * unit;
+      const uint64_t w1 = tau + 1 < ntk ? w0 + unit : wstart[lo] + L + kTaskOverheadBytes * ntk;
+      const bool lead = round_up_to(w0, bucket, inv_bucket) < w1;
+      task_string[task] = (uint32_t)(first + lo) | (lead ? 0x80000000u : 0u);
+      nlead += lead;
+      if (lead && e - e_lo < 64) leads |= 1ull << (e - e_lo);
+    }
   }
   // positions in bucket_lead: one atomic per workgroup (none when it is the
   // only one)
@@ -724,10 +750,14 @@ __device__ void plan_fill_body(
     }
   }
   __syncthreads();
+  // this thread's leaders, in task order (flags past its 64th task read
+  // back from the table it wrote)
   uint32_t at = lead_base + (uint32_t)before;
-  for (uint64_t e = tid; e < blk_t; e += kPlanThreads) {
-    const uint64_t task = task_base + e;
-    if (task_string[task] >> 31) bucket_lead[at++] = (uint32_t)task;
+  if (nlead) {
+    for (uint64_t e = e_lo; e < e_hi; ++e) {
+      const uint64_t task = task_base + e;
+      if (e - e_lo < 64 ? (leads >> (e - e_lo)) & 1 : task_string[task] >> 31) bucket_lead[at++] = (uint32_t)task;
+    }
   }
 }
 
@@ -993,12 +1023,14 @@ __device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F)
 // bytes back into place.  (A direct-to-LDS copy from an address that is not a
 // multiple of 4 costs far more than one from an aligned address, and so does
 // an LDS read at such an offset: strings packed back to back took 1.18-1.20
-// ms either way where the same strings on 8-byte boundaries took 1.03.)  The
-// pieces copied lie in 4-byte-aligned words that hold bytes of the
-// executions, so never past the page of the string's allocation; such
-// strings start mid-block, so cA = C0 and no blocks are carried (cin = cout
-// = 0), and the slots' padding (at least one block past each part) holds the
-// extra piece.
+// ms either way where the same strings on 8-byte boundaries took 1.03.)  Only
+// part A copies the extra piece: its bytes are the execution's own (part B
+// follows), while past part B may lie the end of the string and of its
+// allocation's last page; part B's last word is loaded into a register
+// instead (region_ehc).  So every piece copied holds only words that hold
+// bytes of the executions.  Such strings start mid-block, so cA = C0 and no
+// blocks are carried (cin = cout = 0), and the slots' padding (at least one
+// block past each part) holds the extra piece.
 template <int WIDTH, int B, bool PART_B, bool UNI>
 __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uint32_t qs, uint32_t nq,
                                            uint32_t cnt, lds_u8* stage) {
@@ -1010,7 +1042,7 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
   const uint32_t ca_u = UNI ? part_a_blocks<WIDTH, B>(base) : 0;
   const uint32_t sh = (uint32_t)reinterpret_cast<uintptr_t>(base) & 3u;  // (uniform)
   const uint8_t* const abase = base - sh;
-  const uint32_t wext = sh ? 16u : 0u;
+  const uint32_t wext = sh && !PART_B ? 16u : 0u;
   const uint32_t lane = opaque_lane();
 #pragma unroll
   for (int i = 0; i < (int)S; ++i) {
@@ -1029,9 +1061,10 @@ __device__ __forceinline__ void stage_part(const uint8_t* __restrict__ base, uin
 // whose bytes start sh < 4 bytes into the slot (see stage_part): an aligned
 // 16-byte read and the next word, shifted right by sh bytes (bytes read past
 // the slot's copied ones are not used; the stage buffer has a guard word
-// past its last slot).
-template <int B, int N, int S>
-__device__ __forceinline__ void read_slot(const lds_u8* stage, uint32_t sh, uint4 (&x)[N]) {
+// past its last slot).  KLAST >= 0: the word after block KLAST of the lane
+// group's last lane is `elast` (loaded from HBM: the slot holds no copy).
+template <int B, int N, int S, int KLAST = -1>
+__device__ __forceinline__ void read_slot(const lds_u8* stage, uint32_t sh, uint4 (&x)[N], uint32_t elast = 0) {
   const uint32_t lane = opaque_lane();
   const int q = lane / Geo<B>::LPB, r = lane % Geo<B>::LPB;
   const lds_u8* at = stage + q * (S * 8 * B) + 16 * r;
@@ -1045,7 +1078,8 @@ __device__ __forceinline__ void read_slot(const lds_u8* stage, uint32_t sh, uint
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const u32x4 v = *(lds_u4*)(at + 8 * B * k);
-      const uint32_t e = *(lds_u32*)(at + 8 * B * k + 16);
+      uint32_t e = *(lds_u32*)(at + 8 * B * k + 16);
+      if (k == KLAST && r == Geo<B>::LPB - 1) e = elast;
       x[k] = make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh), __builtin_amdgcn_alignbyte(v.z, v.y, sh),
                         __builtin_amdgcn_alignbyte(v.w, v.z, sh), __builtin_amdgcn_alignbyte(e, v.w, sh));
     }
@@ -1103,12 +1137,18 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
   const uint32_t ca = part_a_blocks<WIDTH, B>(base + (opaque_lane() / Geo<B>::LPB) * qs);
   const uint32_t sh = (uint32_t)reinterpret_cast<uintptr_t>(base) & 3u;
   uint4 xe[LX > 0 ? LX : 1];  // part A's copies of blocks C0 .. C0+LX-1
+  uint32_t eb = 0;             // (sh > 0) the word holding the execution's last bytes
   {
     uint4 x[P::NA];
     wait_vm();
     read_slot<B, P::NA, P::SA>(stage, sh, x);
     wait_lgkm();
     stage_part<WIDTH, B, true, UNI>(base, qs, nq, cout, stage);
+    if (sh) {  // (uniform) read by the lane that shifts the last block's bytes
+      const uint32_t l = opaque_lane(), q = l / Geo<B>::LPB;
+      if (l % Geo<B>::LPB == Geo<B>::LPB - 1 && (UNI || q < nq))
+        eb = *reinterpret_cast<const uint32_t*>(base - sh + q * qs + P::NBLK * P::BB);
+    }
     if (call_hook) hook();  // (e.g. the string's tail loads, in flight with part B)
 #pragma unroll
     for (int k = 0; k < LX; ++k) xe[k] = x[P::C0 + k];
@@ -1120,7 +1160,7 @@ __device__ __forceinline__ void region_ehc(lds_u8* stage, const uint8_t* base, u
   {
     uint4 x[P::NB];
     wait_vm();
-    read_slot<B, P::NB, P::SB>(stage, sh, x);
+    read_slot<B, P::NB, P::SB, P::NBLK - P::C0 - 1>(stage, sh, x, eb);
     wait_lgkm();
     stage_issue<WIDTH, B>(next, ncin, stage);
 #pragma unroll
@@ -2181,9 +2221,10 @@ __device__ __forceinline__ uint64_t* stack_at(uint64_t* stack, int l, int i) {
 // a level-0 item) and then the roots of consecutive aligned blocks (root r
 // at level levels[r]): an item joins its level; the 8th completes the node
 // sum_{i<7} NH(item_i, S_tree[t][l][i]) + item_7, which is pushed one level
-// up.  The occupied levels of the stack are held in LDS while the kernel runs
-// (copied in and back with many loads in flight), and each root is loaded one
-// push ahead.  Last, the update's rest_len trailing bytes at `rest` become the
+// up.  The occupied levels of the stack and the tree keys are held in LDS
+// while the kernel runs (copied in, and the stack back, with many loads in
+// flight), and the roots are loaded kAhead at a time, one chunk ahead of the
+// pushes.  Last, the update's rest_len trailing bytes at `rest` become the
 // carried bytes.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restrict__ ent,
@@ -2199,7 +2240,10 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
   constexpr int kBatch = 16;          // words per lane in flight when copying
   constexpr uint32_t XB = Layout<WIDTH, B>::exec_bytes;
   constexpr int kByteSteps = (int)((XB + 63) / 64);  // byte copies per lane, all in flight
+  constexpr int kKeys = K * kLevels * (kFan - 1);     // tree keys [t][level][i]
+  constexpr int kAhead = 16;                           // roots per chunk
   __shared__ uint64_t lst[kLevels * (kFan - 1) * IW];
+  __shared__ uint64_t lkey[kKeys];
   __shared__ __attribute__((aligned(16))) uint8_t lexec[XB];
   const int lane = threadIdx.x;
   const bool mine = lane < K * B;
@@ -2210,6 +2254,7 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
     return occ ? (64 - __clzll((long long)occ)) * (kFan - 1) * IW : 0;
   };
   const int nin = used_words();
+  for (int i = lane; i < kKeys; i += 64) lkey[i] = ent[Ly::tree + i];
   for (int base = 0; base < nin; base += 64 * kBatch) {
     uint64_t buf[kBatch];
 #pragma unroll
@@ -2237,7 +2282,7 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
       uint64_t node = v;
       if (mine) {
         for (int i = 0; i < kFan - 1; ++i)
-          node = nh_acc(node, lst[(l * (kFan - 1) + i) * IW + w], ent[Ly::tree + (t * kLevels + l) * (kFan - 1) + i]);
+          node = nh_acc(node, lst[(l * (kFan - 1) + i) * IW + w], lkey[(t * kLevels + l) * (kFan - 1) + i]);
       }
       if (lane == l) cnt = 0;
       v = node;
@@ -2270,16 +2315,24 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
     }
     push(0, v);
   }
-  uint64_t nv = nroots && mine ? roots[w] : 0;
-  uint32_t nl = nroots ? levels[0] : 0;
-  for (uint32_t r = 0; r < nroots; ++r) {
-    const uint64_t v = nv;
-    const int l = (int)nl;
-    if (r + 1 < nroots) {
-      nv = mine ? roots[(uint64_t)(r + 1) * IW + w] : 0;
-      nl = levels[r + 1];
-    }
-    push(l, v);
+  // roots: chunk c + 1 in flight while chunk c is pushed (lane u of the
+  // chunk's level word holds root c + u's level)
+  uint64_t cur[kAhead], nxt[kAhead];
+  uint32_t lcur = 0, lnxt = 0;
+  auto load_chunk = [&](uint32_t c, uint64_t(&v)[kAhead], uint32_t& lv) {
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) v[u] = mine && c + u < nroots ? roots[(uint64_t)(c + u) * IW + w] : 0;
+    lv = lane < kAhead && c + lane < nroots ? levels[c + lane] : 0;
+  };
+  if (nroots) load_chunk(0, cur, lcur);
+  for (uint32_t c = 0; c < nroots; c += kAhead) {
+    if (c + kAhead < nroots) load_chunk(c + kAhead, nxt, lnxt);
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u)
+      if (c + u < nroots) push(__shfl((int)lcur, u), cur[u]);
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) cur[u] = nxt[u];
+    lcur = lnxt;
   }
   // occupied levels back to the device stack, and the counts
   const int nout = used_words();
@@ -2332,6 +2385,80 @@ __global__ void stream_table_kernel(uint64_t e0, uint64_t n, uint64_t pos, uint6
     lev[i] = (uint32_t)L;
     ++i;
     x += cnt;
+  }
+}
+
+// The table of a gathered group (GatherWalk): thread k = 1 .. nseg-1 walks
+// the executions of piece k from the state the host's walk had before it
+// (its entries start at w_first[k]), thread nseg the joins after the last
+// piece; then each wave copies the bytes of every fourth join into its slot,
+// and every thread some of the group's trailing bytes (after its last full
+// execution, fewer than one execution) into the carry buffer.  The old
+// carried bytes (segment 0) are all read before the barrier that precedes
+// that write.
+static_assert(kStreamLevels == kLevels, "the stack's levels are the tree's");
+__global__ __launch_bounds__(256) void stream_gather_kernel(GatherArgs g) {
+  constexpr uint32_t kThreads = 256;
+  constexpr int kRest = (8 * 8 * 7 * 3 + kThreads - 1) / kThreads;  // trailing bytes per thread (b = 8, d = 7, w = 3)
+  static_assert(kGatherMax + 1 < (int)kThreads, "a thread per segment");
+  __shared__ uint64_t js[kGatherMax];         // the joins' offsets in the concatenation
+  __shared__ uint64_t segat[kGatherMax + 2];  // segment starts, then the total
+  __shared__ const uint8_t* segp[kGatherMax + 1];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t xb = g.xb;
+  if (tid <= g.nseg) segat[tid] = g.w_at[tid];
+  if (tid < g.nseg) segp[tid] = g.seg[tid];
+  if (tid >= 1 && tid <= g.nseg) {
+    const uintptr_t b = reinterpret_cast<uintptr_t>(g.base);
+    uint32_t i = g.w_first[tid];
+    auto block = [&](uint64_t, int L, const uint8_t* at) {
+      g.off[i] = reinterpret_cast<uintptr_t>(at) - b;
+      g.len[i] = xb << (3 * L);
+      g.lev[i] = (uint32_t)L;
+      ++i;
+    };
+    auto join = [&](uint32_t j, uint64_t s) {
+      js[j] = s;
+      g.off[i] = reinterpret_cast<uintptr_t>(g.joins + j * xb) - b;
+      g.len[i] = xb;
+      g.lev[i] = 0;
+      ++i;
+    };
+    GatherWalk w(xb, g.e0, g.w_at[tid], g.w_next[tid], g.w_nj[tid]);
+    if (tid < g.nseg)
+      w.piece(g.seg[tid], g.seg_len[tid], block, join);
+    else
+      w.finish(join);
+  }
+  __syncthreads();
+  const uint64_t nj = g.nj, r0 = g.nfull * xb, total = segat[g.nseg];
+  // joins: a wave per join, each lane's segment moving forward with its bytes
+  const uint32_t lane = tid % 64, wave = tid / 64;
+  for (uint64_t j = wave; j < nj; j += kThreads / 64) {
+    uint32_t k = 0;
+    for (uint64_t i = lane; i < xb; i += 64) {
+      const uint64_t s = js[j] + i;  // (< total)
+      while (s >= segat[k + 1]) ++k;
+      g.joins[j * xb + i] = segp[k][s - segat[k]];
+    }
+  }
+  uint8_t rest[kRest];
+  uint32_t k = 0;
+#pragma unroll
+  for (int u = 0; u < kRest; ++u) {
+    const uint64_t s = r0 + u * kThreads + tid;
+    if (s < total) {
+      while (s >= segat[k + 1]) ++k;
+      rest[u] = segp[k][s - segat[k]];
+    } else {
+      rest[u] = 0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kRest; ++u) {
+    const uint64_t s = r0 + u * kThreads + tid;
+    if (s < total) g.carry[s - r0] = rest[u];
   }
 }
 
@@ -2579,6 +2706,11 @@ hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* en
 hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
                                uint32_t* lev, hipStream_t stream) {
   hipLaunchKernelGGL(stream_table_kernel, dim3(1), dim3(64), 0, stream, e0, n, pos, xb, off, len, lev);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_gather(const GatherArgs& g, hipStream_t stream) {
+  hipLaunchKernelGGL(stream_gather_kernel, dim3(1), dim3(256), 0, stream, g);
   return hipGetLastError();
 }
 

@@ -11,12 +11,17 @@
 // hashing kernel in root mode computes every block's root in one launch
 // (the blocks are its strings), and a one-wave kernel pushes, in order, the
 // execution completed from the carried bytes (hashing it itself) and the
-// roots onto the device-resident stack.  Finishing hashes the pending items
+// roots onto the device-resident stack.  A gathered update takes several
+// pieces in one call: the blocks inside each piece and the executions that
+// straddle two pieces (assembled in a small buffer) are hashed in one
+// root-mode launch, so pieces too small to fill the device alone fill it
+// together.  Finishing hashes the pending items
 // with the final keys, the pending bytes as the tail and the length.  This
 // file only plans blocks and moves bytes; all hash arithmetic is in the
 // kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -32,6 +37,8 @@ constexpr int kLevelsMax = 20;
 // alignment of the largest block and 7 per level on the way down (with room
 // to spare).
 constexpr uint32_t kMaxRoots = 2 * 7 * kLevelsMax + 8;
+static_assert(kMaxRoots + 1 <= hth::kStreamTable, "one piece's blocks and join fit a table");
+static_assert(kLevelsMax == hth::kStreamLevels, "stack levels");
 constexpr uint32_t kMaxExecBytes = 8 * 8 * 7 * 3;  // largest execution (b = 8, d = 7, w = 3)
 constexpr uint32_t kSaveMagic = 0x48544853;         // "HTHS"
 constexpr uint32_t kSaveVersion = 1;
@@ -57,9 +64,10 @@ struct hth_stream {
   uint32_t* counts = nullptr;
   uint8_t* carry = nullptr;
   uint64_t* roots = nullptr;
-  uint64_t* d_off = nullptr;  // [kMaxRoots] block offsets
-  uint64_t* d_len = nullptr;  // [kMaxRoots] block lengths
-  uint32_t* d_lev = nullptr;  // [kMaxRoots] block levels
+  uint64_t* d_off = nullptr;  // [kStreamTable] block offsets
+  uint64_t* d_len = nullptr;  // [kStreamTable] block lengths
+  uint32_t* d_lev = nullptr;  // [kStreamTable] block levels
+  uint8_t* joins = nullptr;   // [kGatherMax][xb] executions that straddle pieces
   Workspace ws;
 };
 
@@ -104,10 +112,11 @@ hth_status hth_stream_create(const hth_seed* seed, uint32_t out_width, hth_strea
   const size_t o_stack = take((size_t)hth::kStackWords * 8);
   const size_t o_counts = take(32 * 4);
   const size_t o_carry = take(kMaxExecBytes);
-  const size_t o_roots = take((size_t)kMaxRoots * hth::kMaxK * 8 * 8);
-  const size_t o_off = take(kMaxRoots * 8);
-  const size_t o_len = take(kMaxRoots * 8);
-  const size_t o_lev = take(kMaxRoots * 4);
+  const size_t o_roots = take((size_t)hth::kStreamTable * hth::kMaxK * 8 * 8);
+  const size_t o_off = take(hth::kStreamTable * 8);
+  const size_t o_len = take(hth::kStreamTable * 8);
+  const size_t o_lev = take(hth::kStreamTable * 4);
+  const size_t o_joins = take((size_t)hth::kGatherMax * kMaxExecBytes);
   e = hipMalloc(&st->mem, off);
   if (e == hipSuccess) e = hipMemset(st->mem, 0, off);
   if (e != hipSuccess) {
@@ -123,7 +132,8 @@ hth_status hth_stream_create(const hth_seed* seed, uint32_t out_width, hth_strea
   st->d_off = reinterpret_cast<uint64_t*>(b + o_off);
   st->d_len = reinterpret_cast<uint64_t*>(b + o_len);
   st->d_lev = reinterpret_cast<uint32_t*>(b + o_lev);
-  hth_status s = ws_alloc(st->ws, kMaxRoots, nullptr);
+  st->joins = reinterpret_cast<uint8_t*>(b + o_joins);
+  hth_status s = ws_alloc(st->ws, hth::kStreamTable, nullptr);
   if (s != HTH_OK) {
     (void)hipFree(st->mem);
     delete st;
@@ -184,6 +194,99 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   st->carry_len = (uint32_t)rem;
   st->executions = e0 + n;
   st->total_len += len;
+  return HTH_OK;
+}
+
+hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces, const uint64_t* lens,
+                                    uint32_t count, hipStream_t stream) {
+  if (!st) return fail(HTH_E_INVALID, "hth_stream_update_gather: stream is null");
+  if (count == 0) return HTH_OK;
+  if (!pieces || !lens) return fail(HTH_E_INVALID, "hth_stream_update_gather: pieces or lens is null");
+  for (uint32_t i = 0; i < count; ++i)
+    if (lens[i] && !pieces[i]) return fail(HTH_E_INVALID, "hth_stream_update_gather: piece %u is null", i);
+  const uint64_t xb = st->xb;
+  for (uint32_t i = 0; i < count;) {
+    // a group: the carried bytes, then pieces while their table fits
+    hth::GatherArgs g{};
+    g.e0 = st->executions;
+    g.xb = (uint32_t)xb;
+    g.seg[0] = st->carry;
+    g.seg_len[0] = st->carry_len;
+    g.nseg = 1;
+    g.joins = st->joins;
+    g.carry = st->carry;
+    g.off = st->d_off;
+    g.len = st->d_len;
+    g.lev = st->d_lev;
+    hth::GatherWalk w(xb, st->executions, st->carry_len);
+    uint32_t n = 0;  // table entries of the pieces taken (without the joins after the last)
+    uint64_t waves = 0, bytes = 0;
+    auto trailing = [](hth::GatherWalk f) {  // joins after the last piece's blocks
+      uint32_t c = 0;
+      f.finish([&](uint32_t, uint64_t) { ++c; });
+      return c;
+    };
+    for (; i < count && g.nseg <= hth::kGatherMax; ++i) {
+      if (lens[i] == 0) continue;
+      hth::GatherWalk t = w;
+      uint32_t tn = n;
+      uint64_t tw = waves;
+      t.piece(
+          pieces[i], lens[i],
+          [&](uint64_t, int L, const uint8_t*) {
+            ++tn;
+            tw += task_bound(xb << (3 * L), st->width, st->block);
+          },
+          [&](uint32_t, uint64_t) {
+            ++tn;
+            ++tw;
+          });
+      if (tn + trailing(t) > hth::kStreamTable) break;  // (one piece alone always fits: kMaxRoots + 1 entries)
+      g.w_at[g.nseg] = w.at;  // (the walk before the piece, for the table kernel)
+      g.w_next[g.nseg] = w.next;
+      g.w_nj[g.nseg] = w.nj;
+      g.w_first[g.nseg] = n;
+      g.seg[g.nseg] = pieces[i];
+      g.seg_len[g.nseg] = lens[i];
+      ++g.nseg;
+      w = t;
+      n = tn;
+      waves = tw;
+      bytes += lens[i];
+    }
+    if (g.nseg == 1) {
+      if (i < count) return fail(HTH_E_INVALID, "hth_stream_update_gather: piece %u does not fit a table", i);
+      break;  // (only empty pieces were left)
+    }
+    const uint32_t nt = trailing(w);
+    g.w_at[g.nseg] = w.at;
+    g.w_next[g.nseg] = w.next;
+    g.w_nj[g.nseg] = w.nj;
+    g.w_first[g.nseg] = n;
+    g.nj = w.nj + nt;
+    n += nt;
+    waves += nt;
+    const uint64_t nfull = w.at / xb;
+    g.nfull = nfull;
+    // table offsets from the lowest address the hashing kernel reads
+    uintptr_t lo = reinterpret_cast<uintptr_t>(st->joins);
+    for (uint32_t k = 1; k < g.nseg; ++k) lo = std::min(lo, reinterpret_cast<uintptr_t>(g.seg[k]));
+    g.base = reinterpret_cast<const uint8_t*>(lo);
+    hipError_t e = hth::launch_stream_gather(g, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: table");
+    if (n) {
+      hth_status s = launch_blocks(st, g.base, n, waves, stream);
+      if (s != HTH_OK) return s;
+      const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
+      e = hth::launch_stream_push(st->width, st->block, ent, st->carry, 0, nullptr, nullptr, 0, st->roots, st->d_lev,
+                                  n, st->stack, st->counts, stream);
+      if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: push launch");
+    }
+    const uint64_t all = st->carry_len + bytes;
+    st->executions += nfull;
+    st->carry_len = (uint32_t)(all - nfull * xb);
+    st->total_len += bytes;
+  }
   return HTH_OK;
 }
 

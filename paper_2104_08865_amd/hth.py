@@ -33,7 +33,7 @@ SYMBOLS = (
     "hth_expand_seed_b", "hth_seed_from_entropy_b", "hth_seed_block_words", "hth_stream_create",
     "hth_stream_update", "hth_stream_final", "hth_stream_reset", "hth_stream_save", "hth_stream_load",
     "hth_stream_length", "hth_stream_free", "hth_tab_words", "hth_tab_expand", "hth_hash_batch64",
-    "hth_hash_batch_noalloc", "hth_serve_submit_pinned", "hth_serve_replay_pinned",
+    "hth_hash_batch_noalloc", "hth_serve_submit_pinned", "hth_serve_replay_pinned", "hth_stream_update_gather",
 )
 
 
@@ -128,6 +128,7 @@ def lib():
         L.hth_seed_block_words.argtypes = [vp]
         L.hth_stream_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
         L.hth_stream_update.argtypes = [vp, vp, u64, vp]
+        L.hth_stream_update_gather.argtypes = [vp, vp, vp, ctypes.c_uint32, vp]
         L.hth_stream_final.argtypes = [vp, vp, vp]
         L.hth_stream_reset.argtypes = [vp, vp]
         L.hth_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t), vp]
@@ -557,6 +558,21 @@ class Stream:
             raise TypeError("data must be a contiguous uint8 CUDA tensor")
         _check(lib().hth_stream_update(self._h, ctypes.c_void_p(data.data_ptr() if data.numel() else 0),
                                        data.numel(), _stream(stream)))
+        return self
+
+    def update_gather(self, pieces, stream=None):
+        """Append a list of uint8 CUDA tensors in order, their blocks hashed
+        together (hth_stream_update_gather; same value as updating with each
+        in turn).  The tensors must stay alive until the work enqueued on the
+        stream completes."""
+        import torch
+        for d in pieces:
+            if d.dtype != torch.uint8 or not d.is_cuda or not d.is_contiguous():
+                raise TypeError("pieces must be contiguous uint8 CUDA tensors")
+        n = len(pieces)
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[d.data_ptr() if d.numel() else 0 for d in pieces])
+        lens = (ctypes.c_uint64 * max(n, 1))(*[d.numel() for d in pieces])
+        _check(lib().hth_stream_update_gather(self._h, ptrs, lens, n, _stream(stream)))
         return self
 
     def final(self, out=None, stream=None):
