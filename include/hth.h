@@ -309,8 +309,13 @@ hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len,
    (any alignment; lens[i] == 0 is skipped), the pieces may lie in different
    allocations; both host arrays are read during the call, the bytes by the
    work enqueued on `stream` (valid until it completes).  Same ordering rule
-   as hth_stream_update.  Errors: HTH_E_INVALID (null stream, null arrays
-   with count > 0, null piece of non-zero length), HTH_E_HIP. */
+   as hth_stream_update.  Each group's last kernel (the one that folds its
+   results into the stream's state, reading no caller bytes) runs on a HIP
+   stream of the stream object's own, beside the next group's work, ordered
+   by events; every other call on the object waits for it where it must,
+   and hth_stream_free synchronises it (under stream capture it runs on
+   `stream`).  Errors: HTH_E_INVALID (null stream, null arrays with count >
+   0, null piece of non-zero length), HTH_E_HIP. */
 hth_status hth_stream_update_gather(hth_stream *st, const uint8_t *const *pieces, const uint64_t *lens,
                                     uint32_t count, hipStream_t stream);
 
@@ -340,7 +345,8 @@ hth_status hth_stream_load(hth_stream *st, const void *host, size_t size, hipStr
 /* Bytes appended so far (0 for null). */
 uint64_t hth_stream_length(const hth_stream *st);
 
-/* Free a stream (after its enqueued work completed).  Null is accepted. */
+/* Free a stream (after its enqueued work completed; waits for its own
+   internal stream).  Null is accepted. */
 hth_status hth_stream_free(hth_stream *st);
 
 /* ------------------------------------------------------------------------ */

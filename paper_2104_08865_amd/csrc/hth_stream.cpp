@@ -68,6 +68,19 @@ struct hth_stream {
   uint64_t* d_len = nullptr;  // [kStreamTable] block lengths
   uint32_t* d_lev = nullptr;  // [kStreamTable] block levels
   uint8_t* joins = nullptr;   // [kGatherMax][xb] executions that straddle pieces
+  uint64_t* roots2 = nullptr;  // gathered groups alternate between (roots, d_lev) and these
+  uint32_t* d_lev2 = nullptr;
+  // A gathered group's push runs on `side` (a stream of the library's own,
+  // default priority), so it overlaps the next group's table, planner and
+  // hashing launch on the caller's stream: ev_main[b] orders a push after
+  // its group's launch, ev_push[b] a group's table kernel after the push
+  // that last read buffer b.  Everything else that touches the stack waits
+  // for the last push first (join_side).
+  hipStream_t side = nullptr;
+  hipEvent_t ev_main[2] = {nullptr, nullptr}, ev_push[2] = {nullptr, nullptr};
+  uint64_t groups = 0;        // gathered groups so far (group k uses buffer k % 2)
+  bool push_pending = false;  // a push on `side` the caller's stream has not waited for
+  hipEvent_t last_push = nullptr;
   Workspace ws;
 };
 
@@ -76,11 +89,31 @@ namespace {
 hth_status stream_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
 
 // Root-mode hashing of the n blocks of the table (bytes relative to base);
-// roots to st->roots.  waves: an upper bound of their tasks.
-hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint64_t waves, hipStream_t stream) {
+// roots to `roots`.  waves: an upper bound of their tasks.
+hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint64_t waves, uint64_t* roots,
+                         hipStream_t stream) {
   if (n == 0) return HTH_OK;
   return enqueue_batch(st->seed, base, st->d_off, st->d_len, n, nullptr, st->width, st->ws, stream, nullptr, nullptr,
-                       waves, st->roots);
+                       waves, roots);
+}
+
+// The caller's stream waits for the last push on the side stream (before
+// anything that reads or writes the stack, the counts, the carried bytes or
+// buffer 0).
+hth_status join_side(hth_stream* st, hipStream_t stream) {
+  if (!st->push_pending) return HTH_OK;
+  hipError_t e = hipStreamWaitEvent(stream, st->last_push, 0);
+  if (e != hipSuccess) return stream_fail(e, "hth_stream: wait for the previous push");
+  st->push_pending = false;
+  return HTH_OK;
+}
+
+void destroy_side(hth_stream* st) {
+  for (int b = 0; b < 2; ++b) {
+    if (st->ev_main[b]) (void)hipEventDestroy(st->ev_main[b]);
+    if (st->ev_push[b]) (void)hipEventDestroy(st->ev_push[b]);
+  }
+  if (st->side) (void)hipStreamDestroy(st->side);
 }
 
 }  // namespace
@@ -117,6 +150,8 @@ hth_status hth_stream_create(const hth_seed* seed, uint32_t out_width, hth_strea
   const size_t o_len = take(hth::kStreamTable * 8);
   const size_t o_lev = take(hth::kStreamTable * 4);
   const size_t o_joins = take((size_t)hth::kGatherMax * kMaxExecBytes);
+  const size_t o_roots2 = take((size_t)hth::kStreamTable * hth::kMaxK * 8 * 8);
+  const size_t o_lev2 = take(hth::kStreamTable * 4);
   e = hipMalloc(&st->mem, off);
   if (e == hipSuccess) e = hipMemset(st->mem, 0, off);
   if (e != hipSuccess) {
@@ -133,8 +168,22 @@ hth_status hth_stream_create(const hth_seed* seed, uint32_t out_width, hth_strea
   st->d_len = reinterpret_cast<uint64_t*>(b + o_len);
   st->d_lev = reinterpret_cast<uint32_t*>(b + o_lev);
   st->joins = reinterpret_cast<uint8_t*>(b + o_joins);
+  st->roots2 = reinterpret_cast<uint64_t*>(b + o_roots2);
+  st->d_lev2 = reinterpret_cast<uint32_t*>(b + o_lev2);
+  e = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&st->ev_main[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_push[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    destroy_side(st);
+    (void)hipFree(st->mem);
+    delete st;
+    return hip_fail(e, "hth_stream_create: side stream");
+  }
   hth_status s = ws_alloc(st->ws, hth::kStreamTable, nullptr);
   if (s != HTH_OK) {
+    destroy_side(st);
     (void)hipFree(st->mem);
     delete st;
     return s;
@@ -147,6 +196,8 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   if (!st) return fail(HTH_E_INVALID, "hth_stream_update: stream is null");
   if (len && !bytes) return fail(HTH_E_INVALID, "hth_stream_update: bytes is null");
   if (len == 0) return HTH_OK;
+  hth_status js = join_side(st, stream);
+  if (js != HTH_OK) return js;
   const uint64_t xb = st->xb;
   hipError_t e;
   if (st->carry_len + len < xb) {
@@ -180,7 +231,7 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   if (nblocks) {
     e = hth::launch_stream_table(e0, n, pos, xb, st->d_off, st->d_len, st->d_lev, stream);
     if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
-    hth_status s = launch_blocks(st, bytes, nblocks, waves, stream);
+    hth_status s = launch_blocks(st, bytes, nblocks, waves, st->roots, stream);
     if (s != HTH_OK) return s;
   }
   // 3. push the completed execution and the roots, in order; 4. the bytes
@@ -204,6 +255,15 @@ hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces
   if (!pieces || !lens) return fail(HTH_E_INVALID, "hth_stream_update_gather: pieces or lens is null");
   for (uint32_t i = 0; i < count; ++i)
     if (lens[i] && !pieces[i]) return fail(HTH_E_INVALID, "hth_stream_update_gather: piece %u is null", i);
+  // (under stream capture every push stays on the captured stream)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t ce = hipStreamIsCapturing(stream, &cap);
+  if (ce != hipSuccess) return stream_fail(ce, "hth_stream_update_gather: capture status");
+  const bool on_side = cap == hipStreamCaptureStatusNone;
+  if (!on_side) {
+    hth_status js = join_side(st, stream);
+    if (js != HTH_OK) return js;
+  }
   const uint64_t xb = st->xb;
   for (uint32_t i = 0; i < count;) {
     // a group: the carried bytes, then pieces while their table fits
@@ -217,7 +277,9 @@ hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces
     g.carry = st->carry;
     g.off = st->d_off;
     g.len = st->d_len;
-    g.lev = st->d_lev;
+    const int bsel = (int)(st->groups % 2);  // the group's roots and levels
+    uint64_t* const roots = bsel ? st->roots2 : st->roots;
+    g.lev = bsel ? st->d_lev2 : st->d_lev;
     hth::GatherWalk w(xb, st->executions, st->carry_len);
     uint32_t n = 0;  // table entries of the pieces taken (without the joins after the last)
     uint64_t waves = 0, bytes = 0;
@@ -272,15 +334,30 @@ hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces
     uintptr_t lo = reinterpret_cast<uintptr_t>(st->joins);
     for (uint32_t k = 1; k < g.nseg; ++k) lo = std::min(lo, reinterpret_cast<uintptr_t>(g.seg[k]));
     g.base = reinterpret_cast<const uint8_t*>(lo);
-    hipError_t e = hth::launch_stream_gather(g, stream);
+    // (the levels of buffer bsel were last read by the push two groups back)
+    hipError_t e = on_side ? hipStreamWaitEvent(stream, st->ev_push[bsel], 0) : hipSuccess;
+    if (e == hipSuccess) e = hth::launch_stream_gather(g, stream);
     if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: table");
     if (n) {
-      hth_status s = launch_blocks(st, g.base, n, waves, stream);
+      hth_status s = launch_blocks(st, g.base, n, waves, roots, stream);
       if (s != HTH_OK) return s;
+      hipStream_t ps = stream;
+      if (on_side) {  // the push after this group's launch, beside the next group's work
+        e = hipEventRecord(st->ev_main[bsel], stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st->side, st->ev_main[bsel], 0);
+        if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: order the push");
+        ps = st->side;
+      }
       const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
-      e = hth::launch_stream_push(st->width, st->block, ent, st->carry, 0, nullptr, nullptr, 0, st->roots, st->d_lev,
-                                  n, st->stack, st->counts, stream);
+      e = hth::launch_stream_push(st->width, st->block, ent, st->carry, 0, nullptr, nullptr, 0, roots, g.lev, n,
+                                  st->stack, st->counts, ps);
+      if (e == hipSuccess && on_side) e = hipEventRecord(st->ev_push[bsel], st->side);
       if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: push launch");
+      if (on_side) {
+        st->last_push = st->ev_push[bsel];
+        st->push_pending = true;
+      }
+      ++st->groups;
     }
     const uint64_t all = st->carry_len + bytes;
     st->executions += nfull;
@@ -292,6 +369,8 @@ hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces
 
 hth_status hth_stream_final(hth_stream* st, uint8_t* out, hipStream_t stream) {
   if (!st || !out) return fail(HTH_E_INVALID, "hth_stream_final: null pointer");
+  hth_status js = join_side(st, stream);
+  if (js != HTH_OK) return js;
   const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
   hipError_t e = hth::launch_stream_final(st->width, st->block, ent, st->stack, st->counts, st->carry, st->carry_len,
                                           st->total_len, out, stream);
@@ -301,6 +380,8 @@ hth_status hth_stream_final(hth_stream* st, uint8_t* out, hipStream_t stream) {
 
 hth_status hth_stream_reset(hth_stream* st, hipStream_t stream) {
   if (!st) return fail(HTH_E_INVALID, "hth_stream_reset: stream is null");
+  hth_status js = join_side(st, stream);
+  if (js != HTH_OK) return js;
   hipError_t e = hipMemsetAsync(st->counts, 0, 32 * 4, stream);
   if (e != hipSuccess) return stream_fail(e, "hth_stream_reset");
   st->executions = st->total_len = 0;
@@ -316,6 +397,8 @@ hth_status hth_stream_save(hth_stream* st, void* host, size_t* size, hipStream_t
     return HTH_OK;
   }
   if (*size < need) return fail(HTH_E_TOO_LARGE, "hth_stream_save: buffer of %zu bytes, %zu needed", *size, need);
+  hth_status js = join_side(st, stream);
+  if (js != HTH_OK) return js;
   SaveHeader h{kSaveMagic, kSaveVersion, st->width, st->block, st->executions, st->total_len, st->carry_len, 0};
   char* p = static_cast<char*>(host);
   std::memcpy(p, &h, sizeof h);
@@ -361,6 +444,8 @@ hth_status hth_stream_load(hth_stream* st, const void* host, size_t size, hipStr
   if (h.executions > (UINT64_MAX - h.carry_len) / st->xb || h.total_len != h.executions * st->xb + h.carry_len)
     return fail(HTH_E_INVALID, "hth_stream_load: %llu bytes do not match %llu executions and %u carried bytes",
                 (unsigned long long)h.total_len, (unsigned long long)h.executions, h.carry_len);
+  hth_status js = join_side(st, stream);
+  if (js != HTH_OK) return js;
   hipError_t e = hipMemcpyAsync(st->counts, p + sizeof h, kLevelsMax * 4, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(st->stack, p + sizeof h + kLevelsMax * 4, (size_t)hth::kStackWords * 8, hipMemcpyHostToDevice,
@@ -380,7 +465,10 @@ uint64_t hth_stream_length(const hth_stream* st) { return st ? st->total_len : 0
 
 hth_status hth_stream_free(hth_stream* st) {
   if (!st) return HTH_OK;
-  hipError_t e = hipFree(st->mem);
+  hipError_t e = st->side ? hipStreamSynchronize(st->side) : hipSuccess;  // (a push may still run)
+  destroy_side(st);
+  hipError_t f0 = hipFree(st->mem);
+  if (e == hipSuccess) e = f0;
   if (st->ws.mem) {
     hipError_t f = hipFree(st->ws.mem);
     if (e == hipSuccess) e = f;

@@ -304,3 +304,32 @@ def test_stream_gather_argument_errors(env):
     assert len(st) == 0
     assert (st.final().cpu().numpy() == o.hash_bytes(o.expand_seed(56), b"", 16)).all()
     st.free()
+
+
+def test_stream_gather_back_to_back_calls(env):
+    """Twelve gathered calls in a row with nothing between them (each call's
+    push runs beside the next call's hashing, the two root buffers taking
+    turns), then the value; reset and free right after a gathered call."""
+    torch, hth, o = env["torch"], env["hth"], env["oracle"]
+    width, xb = 40, wl.execution_bytes(40)
+    seed = hth.expand_seed(57)
+    ent = o.expand_seed(57)
+    rng = np.random.default_rng(58)
+    lens = [int(rng.integers(0, 900 * xb)) for _ in range(36)]
+    total = sum(lens)
+    data_np = wl.random_bytes(59, total)
+    data = torch.from_numpy(data_np).cuda()
+    views = _views(torch, data, lens, own_every=4)
+    st = hth.Stream(seed, width)
+    for c in range(0, 36, 3):
+        st.update_gather(views[c:c + 3])
+    assert (st.final().cpu().numpy() == o.hash_bytes(ent, data_np, width)).all()
+    st.update_gather(views[:5])
+    st.reset()
+    st.update_gather(views[:2])
+    st.update(views[2])
+    at = lens[0] + lens[1] + lens[2]
+    assert (st.final().cpu().numpy() == o.hash_bytes(ent, data_np[:at], width)).all()
+    st.update_gather(views[3:9])
+    st.free()  # (its last push may still be running)
+    torch.cuda.synchronize()
