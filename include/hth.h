@@ -287,7 +287,8 @@ hth_status hth_set_tuning(uint32_t out_width, uint32_t waves_per_cu, uint32_t mi
 typedef struct hth_stream hth_stream;
 
 /* Create an empty stream for `seed` (its family) and out_width.  Allocates
-   its device state (about 400 KB) and a planning workspace; synchronous.
+   its device state (about 0.8 MB), a planning workspace and a HIP stream of
+   its own (default priority, for hth_stream_update_gather); synchronous.
    The seed must outlive the stream.  Errors: HTH_E_INVALID (null pointer,
    bad out_width, seed on another device), HTH_E_OOM, HTH_E_HIP. */
 hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_stream **out);
