@@ -60,6 +60,27 @@ def test_small_batch(env, width):
 
 
 @pytest.mark.parametrize("width", WIDTHS)
+def test_unaligned_strings_with_short_tails(env, width):
+    """Strings of N executions plus T < 16 bytes starting sh = 1, 2, 3 bytes
+    past a 4-byte boundary (hashed by the hashing kernel: N >= 9), the last
+    one ending at the end of the buffer: the staged copies of such strings
+    stop at each execution's end and the word holding its last bytes comes
+    from a separate load, which these values pin."""
+    xb = wl.execution_bytes(width)
+    offs, lens, at = [], [], 0
+    for n in (9, 16, 17, 64, 129):
+        for t in range(16):
+            for sh in (1, 2, 3):
+                at = (at + 3) // 4 * 4 + sh
+                offs.append(at)
+                lens.append(n * xb + t)
+                at += n * xb + t
+    data = wl.random_bytes(12, at)  # (exactly as long as the strings need)
+    _check(env, data, np.asarray(offs, dtype=np.uint64), np.asarray(lens, dtype=np.uint64), width,
+           "unaligned strings with short tails")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
 def test_every_length_to_1400_and_odd_offsets(env, width):
     lens = np.arange(0, 1401, dtype=np.uint64)
     offs, total = wl.pack(lens)
