@@ -61,6 +61,25 @@ def test_b4_every_length_to_1400(env, width):
 
 
 @pytest.mark.parametrize("width", WIDTHS)
+def test_b4_unaligned_strings_with_short_tails(env, width):
+    """Strings of 9 .. 257 executions plus T < 16 bytes starting 1, 2, 3
+    bytes past a 4-byte boundary, the last one ending at the end of the
+    buffer (the staged path's last word of each execution loaded on its own)."""
+    xb = xb4(width)
+    offs, lens, at = [], [], 0
+    for n in (9, 32, 33, 257):
+        for t in range(16):
+            for sh in (1, 2, 3):
+                at = (at + 3) // 4 * 4 + sh
+                offs.append(at)
+                lens.append(n * xb + t)
+                at += n * xb + t
+    data = wl.random_bytes(32, at)
+    _check(env, data, np.asarray(offs, dtype=np.uint64), np.asarray(lens, dtype=np.uint64), width,
+           "unaligned strings with short tails")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
 def test_b4_tree_boundaries(env, width):
     """Execution counts around the 256-execution pass, the level-3 (512) and
     level-4 (4096) boundaries, and with many base-8 digits set."""
