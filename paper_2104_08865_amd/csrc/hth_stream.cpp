@@ -15,10 +15,11 @@
 // pieces in one call: the blocks inside each piece and the executions that
 // straddle two pieces (assembled in a small buffer) are hashed in one
 // root-mode launch, so pieces too small to fill the device alone fill it
-// together.  Finishing hashes the pending items
-// with the final keys, the pending bytes as the tail and the length.  This
-// file only plans blocks and moves bytes; all hash arithmetic is in the
-// kernels.
+// together; a group's push runs on the stream object's own HIP stream,
+// beside the next group's work.  Finishing hashes the pending items with
+// the final keys, the pending bytes as the tail and the length.  This file
+// only plans blocks, orders launches and moves bytes; all hash arithmetic is
+// in the kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
