@@ -296,7 +296,9 @@ hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_strea
 /* Append `len` bytes at device pointer `bytes` (any alignment), enqueued on
    `stream`; the bytes must stay valid until that work completes.  Every
    call on one hth_stream must be ordered (the same HIP stream, or
-   synchronised).  len == 0 is a no-op.  Errors: HTH_E_INVALID, HTH_E_HIP. */
+   synchronised).  len == 0 is a no-op.  Errors: HTH_E_INVALID (nothing
+   enqueued), HTH_E_HIP (the state may be partly advanced: reset or load it
+   before further use). */
 hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len, hipStream_t stream);
 
 /* Append `count` pieces in order: the same state as `count` calls of
@@ -316,7 +318,8 @@ hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len,
    by events; every other call on the object waits for it where it must,
    and hth_stream_free synchronises it (under stream capture it runs on
    `stream`).  Errors: HTH_E_INVALID (null stream, null arrays with count >
-   0, null piece of non-zero length), HTH_E_HIP. */
+   0, null piece of non-zero length; nothing enqueued), HTH_E_HIP (as for
+   hth_stream_update). */
 hth_status hth_stream_update_gather(hth_stream *st, const uint8_t *const *pieces, const uint64_t *lens,
                                     uint32_t count, hipStream_t stream);
 
