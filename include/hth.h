@@ -296,9 +296,11 @@ hth_status hth_stream_create(const hth_seed *seed, uint32_t out_width, hth_strea
 /* Append `len` bytes at device pointer `bytes` (any alignment), enqueued on
    `stream`; the bytes must stay valid until that work completes.  Every
    call on one hth_stream must be ordered (the same HIP stream, or
-   synchronised).  len == 0 is a no-op.  Errors: HTH_E_INVALID (nothing
-   enqueued), HTH_E_HIP (the state may be partly advanced: reset or load it
-   before further use). */
+   synchronised).  len == 0 is a no-op.  Works as hth_stream_update_gather
+   with one piece (its last kernel on the stream object's own stream); an
+   update that completes no execution is one copy onto the carried bytes.
+   Errors: HTH_E_INVALID (nothing enqueued), HTH_E_HIP (the state may be
+   partly advanced: reset or load it before further use). */
 hth_status hth_stream_update(hth_stream *st, const uint8_t *bytes, uint64_t len, hipStream_t stream);
 
 /* Append `count` pieces in order: the same state as `count` calls of

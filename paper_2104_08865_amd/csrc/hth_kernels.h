@@ -144,17 +144,11 @@ constexpr int kTabThreads = 1024;
 // strings.  The stack holds kLevels x 7 items of kMaxK x 8 words.
 constexpr int kStackWords = 20 * 7 * kMaxK * 8;
 hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint32_t grid, hipStream_t stream);
-// Pushes the EHC of the execution made of the carry_len bytes at `carry`
-// and the first XB - carry_len bytes at `head` (when carry_len > 0) as a
-// level-0 item, then the nroots roots; then copies the rest_len bytes at
-// `rest` (fewer than XB) to `carry`.
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, uint8_t* carry,
-                              uint32_t carry_len, const uint8_t* head, const uint8_t* rest, uint32_t rest_len,
-                              const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
-                              uint32_t* counts, hipStream_t stream);
-// The block table of one update (device arrays), as the host plans it.
-hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
-                               uint32_t* lev, hipStream_t stream);
+// Pushes the nroots roots (levels[r]: the level of root r) onto the stack,
+// closing full nodes upwards.
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
+                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
+                              hipStream_t stream);
 
 // Gathered update: a group of pieces appended with one root-mode launch.
 // Segment 0 is the carried bytes, segments 1 .. nseg-1 the pieces; their

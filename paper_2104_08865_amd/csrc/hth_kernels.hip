@@ -2215,22 +2215,15 @@ __device__ __forceinline__ uint64_t* stack_at(uint64_t* stack, int l, int i) {
   return stack + ((uint64_t)l * (kFan - 1) + i) * (kMaxK * kBlock);
 }
 
-// Push, in order, the execution completed from carried bytes (when
-// carry_len > 0: the carry_len bytes in `carry` followed by the first
-// bytes of the update at `head`, assembled in LDS; its EHC is computed here,
-// a level-0 item) and then the roots of consecutive aligned blocks (root r
-// at level levels[r]): an item joins its level; the 8th completes the node
+// Push the nroots roots of consecutive aligned blocks, in order (root r at
+// level levels[r]): an item joins its level; the 8th completes the node
 // sum_{i<7} NH(item_i, S_tree[t][l][i]) + item_7, which is pushed one level
 // up.  The occupied levels of the stack and the tree keys are held in LDS
 // while the kernel runs (copied in, and the stack back, with many loads in
 // flight), and the roots are loaded kAhead at a time, one chunk ahead of the
-// pushes.  Last, the update's rest_len trailing bytes at `rest` become the
-// carried bytes.
+// pushes.
 template <int WIDTH, int B>
 __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restrict__ ent,
-                                                         uint8_t* __restrict__ carry, uint32_t carry_len,
-                                                         const uint8_t* __restrict__ head,
-                                                         const uint8_t* __restrict__ rest, uint32_t rest_len,
                                                          const uint64_t* __restrict__ roots,
                                                          const uint32_t* __restrict__ levels, uint32_t nroots,
                                                          uint64_t* __restrict__ stack, uint32_t* __restrict__ counts) {
@@ -2238,13 +2231,10 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
   constexpr int K = Family<WIDTH>::K;
   constexpr int IW = kMaxK * kBlock;  // words per stack item, [t][j]
   constexpr int kBatch = 16;          // words per lane in flight when copying
-  constexpr uint32_t XB = Layout<WIDTH, B>::exec_bytes;
-  constexpr int kByteSteps = (int)((XB + 63) / 64);  // byte copies per lane, all in flight
   constexpr int kKeys = K * kLevels * (kFan - 1);     // tree keys [t][level][i]
   constexpr int kAhead = 16;                           // roots per chunk
   __shared__ uint64_t lst[kLevels * (kFan - 1) * IW];
   __shared__ uint64_t lkey[kKeys];
-  __shared__ __attribute__((aligned(16))) uint8_t lexec[XB];
   const int lane = threadIdx.x;
   const bool mine = lane < K * B;
   const int t = lane / B, j = lane % B, w = t * kBlock + j;
@@ -2289,32 +2279,6 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
       ++l;
     }
   };
-  if (carry_len) {
-    // the completed execution in LDS: carried bytes, then the update's first
-    uint8_t bytes[kByteSteps];
-#pragma unroll
-    for (int u = 0; u < kByteSteps; ++u) {
-      const uint32_t i = (uint32_t)(u * 64 + lane);
-      bytes[u] = i < XB ? (i < carry_len ? carry[i] : head[i - carry_len]) : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kByteSteps; ++u) {
-      const uint32_t i = (uint32_t)(u * 64 + lane);
-      if (i < XB) lexec[i] = bytes[u];
-    }
-    __syncthreads();
-    // its EHC: lane r of the first lane group holds instances 2r and 2r + 1
-    // (every lane group computes the same values)
-    uint64_t z0[K], z1[K];
-    ehc2<WIDTH, B>(lexec + 16 * (lane % Geo<B>::LPB), uniform_keys(ent + Ly::ehc), z0, z1);
-    uint64_t v = 0;
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      const uint64_t a0 = shfl64(z0[u], j >> 1), a1 = shfl64(z1[u], j >> 1);
-      if (u == t) v = (j & 1) ? a1 : a0;
-    }
-    push(0, v);
-  }
   // roots: chunk c + 1 in flight while chunk c is pushed (lane u of the
   // chunk's level word holds root c + u's level)
   uint64_t cur[kAhead], nxt[kAhead];
@@ -2350,42 +2314,6 @@ __global__ __launch_bounds__(64) void stream_push_kernel(const uint64_t* __restr
     }
   }
   if (lane < kLevels) counts[lane] = cnt;
-  // the trailing bytes start the next execution (the old carried bytes were
-  // read above, before the barrier)
-  {
-    uint8_t bytes[kByteSteps];
-#pragma unroll
-    for (int u = 0; u < kByteSteps; ++u) {
-      const uint32_t i = (uint32_t)(u * 64 + lane);
-      bytes[u] = i < rest_len ? rest[i] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kByteSteps; ++u) {
-      const uint32_t i = (uint32_t)(u * 64 + lane);
-      if (i < rest_len) carry[i] = bytes[u];
-    }
-  }
-}
-
-// The block table of one update: the maximal aligned blocks of executions
-// e0 .. e0 + n - 1 (block offsets relative to the update's bytes, starting
-// `pos` bytes in).  One thread: a few hundred entries at most; it keeps the
-// table off the host path.
-__global__ void stream_table_kernel(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb,
-                                    uint64_t* __restrict__ off, uint64_t* __restrict__ len,
-                                    uint32_t* __restrict__ lev) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t i = 0;
-  for (uint64_t x = e0, end = e0 + n; x < end;) {
-    int L = 0;
-    while (L + 1 < kLevels && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
-    const uint64_t cnt = 1ull << (3 * L);
-    off[i] = pos + (x - e0) * xb;
-    len[i] = cnt * xb;
-    lev[i] = (uint32_t)L;
-    ++i;
-    x += cnt;
-  }
 }
 
 // The table of a gathered group (GatherWalk): thread k = 1 .. nseg-1 walks
@@ -2689,23 +2617,16 @@ hipError_t launch_roots(uint32_t width, uint32_t block, const MainArgs& a, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, uint8_t* carry,
-                              uint32_t carry_len, const uint8_t* head, const uint8_t* rest, uint32_t rest_len,
-                              const uint64_t* roots, const uint32_t* levels, uint32_t nroots, uint64_t* stack,
-                              uint32_t* counts, hipStream_t stream) {
+hipError_t launch_stream_push(uint32_t width, uint32_t block, const uint64_t* ent, const uint64_t* roots,
+                              const uint32_t* levels, uint32_t nroots, uint64_t* stack, uint32_t* counts,
+                              hipStream_t stream) {
   bool known = false;
   HTH_DISPATCH(width, block, {
-    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, carry, carry_len, head, rest,
-                       rest_len, roots, levels, nroots, stack, counts);
+    hipLaunchKernelGGL((stream_push_kernel<W, Bk>), dim3(1), dim3(64), 0, stream, ent, roots, levels, nroots, stack,
+                       counts);
     known = true;
   });
   if (!known) return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_stream_table(uint64_t e0, uint64_t n, uint64_t pos, uint64_t xb, uint64_t* off, uint64_t* len,
-                               uint32_t* lev, hipStream_t stream) {
-  hipLaunchKernelGGL(stream_table_kernel, dim3(1), dim3(64), 0, stream, e0, n, pos, xb, off, len, lev);
   return hipGetLastError();
 }
 

@@ -103,7 +103,8 @@ hth_status launch_blocks(hth_stream* st, const uint8_t* base, uint32_t n, uint64
 // buffer 0).
 hth_status join_side(hth_stream* st, hipStream_t stream) {
   if (!st->push_pending) return HTH_OK;
-  hipError_t e = hipStreamWaitEvent(stream, st->last_push, 0);
+  hipError_t e = hipEventQuery(st->last_push);  // (done: nothing to wait for)
+  if (e == hipErrorNotReady) e = hipStreamWaitEvent(stream, st->last_push, 0);
   if (e != hipSuccess) return stream_fail(e, "hth_stream: wait for the previous push");
   st->push_pending = false;
   return HTH_OK;
@@ -115,6 +116,125 @@ void destroy_side(hth_stream* st) {
     if (st->ev_push[b]) (void)hipEventDestroy(st->ev_push[b]);
   }
   if (st->side) (void)hipStreamDestroy(st->side);
+}
+
+// The pieces appended in groups (hth_stream_update_gather; a plain update is a
+// group of one piece).  Arguments are checked by the callers.
+hth_status append_groups(hth_stream* st, const uint8_t* const* pieces, const uint64_t* lens, uint32_t count,
+                         hipStream_t stream) {
+  // (under stream capture every push stays on the captured stream)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t ce = hipStreamIsCapturing(stream, &cap);
+  if (ce != hipSuccess) return stream_fail(ce, "hth_stream update: capture status");
+  const bool on_side = cap == hipStreamCaptureStatusNone;
+  if (!on_side) {
+    hth_status js = join_side(st, stream);
+    if (js != HTH_OK) return js;
+  }
+  const uint64_t xb = st->xb;
+  for (uint32_t i = 0; i < count;) {
+    // a group: the carried bytes, then pieces while their table fits
+    hth::GatherArgs g{};
+    g.e0 = st->executions;
+    g.xb = (uint32_t)xb;
+    g.seg[0] = st->carry;
+    g.seg_len[0] = st->carry_len;
+    g.nseg = 1;
+    g.joins = st->joins;
+    g.carry = st->carry;
+    g.off = st->d_off;
+    g.len = st->d_len;
+    const int bsel = (int)(st->groups % 2);  // the group's roots and levels
+    uint64_t* const roots = bsel ? st->roots2 : st->roots;
+    g.lev = bsel ? st->d_lev2 : st->d_lev;
+    hth::GatherWalk w(xb, st->executions, st->carry_len);
+    uint32_t n = 0;  // table entries of the pieces taken (without the joins after the last)
+    uint64_t waves = 0, bytes = 0;
+    auto trailing = [](hth::GatherWalk f) {  // joins after the last piece's blocks
+      uint32_t c = 0;
+      f.finish([&](uint32_t, uint64_t) { ++c; });
+      return c;
+    };
+    for (; i < count && g.nseg <= hth::kGatherMax; ++i) {
+      if (lens[i] == 0) continue;
+      hth::GatherWalk t = w;
+      uint32_t tn = n;
+      uint64_t tw = waves;
+      t.piece(
+          pieces[i], lens[i],
+          [&](uint64_t, int L, const uint8_t*) {
+            ++tn;
+            tw += task_bound(xb << (3 * L), st->width, st->block);
+          },
+          [&](uint32_t, uint64_t) {
+            ++tn;
+            ++tw;
+          });
+      if (tn + trailing(t) > hth::kStreamTable) break;  // (one piece alone always fits: kMaxRoots + 1 entries)
+      g.w_at[g.nseg] = w.at;  // (the walk before the piece, for the table kernel)
+      g.w_next[g.nseg] = w.next;
+      g.w_nj[g.nseg] = w.nj;
+      g.w_first[g.nseg] = n;
+      g.seg[g.nseg] = pieces[i];
+      g.seg_len[g.nseg] = lens[i];
+      ++g.nseg;
+      w = t;
+      n = tn;
+      waves = tw;
+      bytes += lens[i];
+    }
+    if (g.nseg == 1) {
+      if (i < count) return fail(HTH_E_INVALID, "hth_stream update: piece %u does not fit a table", i);
+      break;  // (only empty pieces were left)
+    }
+    const uint32_t nt = trailing(w);
+    g.w_at[g.nseg] = w.at;
+    g.w_next[g.nseg] = w.next;
+    g.w_nj[g.nseg] = w.nj;
+    g.w_first[g.nseg] = n;
+    g.nj = w.nj + nt;
+    n += nt;
+    waves += nt;
+    const uint64_t nfull = w.at / xb;
+    g.nfull = nfull;
+    // table offsets from the lowest address the hashing kernel reads
+    uintptr_t lo = reinterpret_cast<uintptr_t>(st->joins);
+    for (uint32_t k = 1; k < g.nseg; ++k) lo = std::min(lo, reinterpret_cast<uintptr_t>(g.seg[k]));
+    g.base = reinterpret_cast<const uint8_t*>(lo);
+    // (the levels of buffer bsel were last read by the push two groups back)
+    // (a wait across queues costs the stream ≈ 10 us even when the event has
+    // long completed: it is enqueued only if the push is still running)
+    hipError_t e = hipSuccess;
+    if (on_side && (e = hipEventQuery(st->ev_push[bsel])) == hipErrorNotReady)
+      e = hipStreamWaitEvent(stream, st->ev_push[bsel], 0);
+    if (e == hipSuccess) e = hth::launch_stream_gather(g, stream);
+    if (e != hipSuccess) return stream_fail(e, "hth_stream update: table");
+    if (n) {
+      hth_status s = launch_blocks(st, g.base, n, waves, roots, stream);
+      if (s != HTH_OK) return s;
+      hipStream_t ps = stream;
+      if (on_side) {  // the push after this group's launch, beside the next group's work
+        e = hipEventRecord(st->ev_main[bsel], stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st->side, st->ev_main[bsel], 0);
+        if (e != hipSuccess) return stream_fail(e, "hth_stream update: order the push");
+        ps = st->side;
+      }
+      const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
+      e = hth::launch_stream_push(st->width, st->block, ent, roots, g.lev, n, st->stack, st->counts, ps);
+      if (e == hipSuccess && on_side) e = hipEventRecord(st->ev_push[bsel], st->side);
+      if (e != hipSuccess) return stream_fail(e, "hth_stream update: push launch");
+      if (on_side) {
+        st->last_push = st->ev_push[bsel];
+        st->push_pending = true;
+      }
+      ++st->groups;
+    }
+    const uint64_t all = st->carry_len + bytes;
+    st->executions += nfull;
+    st->carry_len = (uint32_t)(all - nfull * xb);
+    st->total_len += bytes;
+  }
+  return HTH_OK;
 }
 
 }  // namespace
@@ -197,56 +317,14 @@ hth_status hth_stream_update(hth_stream* st, const uint8_t* bytes, uint64_t len,
   if (!st) return fail(HTH_E_INVALID, "hth_stream_update: stream is null");
   if (len && !bytes) return fail(HTH_E_INVALID, "hth_stream_update: bytes is null");
   if (len == 0) return HTH_OK;
-  hth_status js = join_side(st, stream);
-  if (js != HTH_OK) return js;
-  const uint64_t xb = st->xb;
-  hipError_t e;
-  if (st->carry_len + len < xb) {
-    e = hipMemcpyAsync(st->carry + st->carry_len, bytes, len, hipMemcpyDeviceToDevice, stream);
+  if (st->carry_len + len < st->xb) {  // no execution completed: the bytes join the carried ones
+    hipError_t e = hipMemcpyAsync(st->carry + st->carry_len, bytes, len, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return stream_fail(e, "hth_stream_update: carry copy");
     st->carry_len += (uint32_t)len;
     st->total_len += len;
     return HTH_OK;
   }
-  // 1. the execution completed from the carried bytes and the update's
-  // first xb - carry_len bytes (assembled and hashed by the push kernel: a
-  // level-0 item)
-  uint64_t pos = 0, e0 = st->executions;
-  if (st->carry_len) {
-    pos = xb - st->carry_len;
-    ++e0;
-  }
-  // 2. the update's full executions, cut into maximal aligned blocks: the
-  // table is written on the device; the host only counts its entries
-  const uint64_t n = (len - pos) / xb;
-  uint32_t nblocks = 0;
-  uint64_t waves = 0;
-  for (uint64_t x = e0, end = e0 + n; x < end;) {
-    int L = 0;
-    while (L + 1 < kLevelsMax && x % (1ull << (3 * (L + 1))) == 0 && x + (1ull << (3 * (L + 1))) <= end) ++L;
-    const uint64_t cnt = 1ull << (3 * L);
-    waves += task_bound(cnt * xb, st->width, st->block);
-    ++nblocks;
-    x += cnt;
-  }
-  if (nblocks) {
-    e = hth::launch_stream_table(e0, n, pos, xb, st->d_off, st->d_len, st->d_lev, stream);
-    if (e != hipSuccess) return stream_fail(e, "hth_stream_update: block table");
-    hth_status s = launch_blocks(st, bytes, nblocks, waves, st->roots, stream);
-    if (s != HTH_OK) return s;
-  }
-  // 3. push the completed execution and the roots, in order; 4. the bytes
-  // after the last full execution start the next one (copied by the same
-  // kernel, after it has read the old carried bytes)
-  const uint64_t rem = len - pos - n * xb;
-  const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
-  e = hth::launch_stream_push(st->width, st->block, ent, st->carry, st->carry_len, bytes, bytes + pos + n * xb,
-                              (uint32_t)rem, st->roots, st->d_lev, nblocks, st->stack, st->counts, stream);
-  if (e != hipSuccess) return stream_fail(e, "hth_stream_update: push launch");
-  st->carry_len = (uint32_t)rem;
-  st->executions = e0 + n;
-  st->total_len += len;
-  return HTH_OK;
+  return append_groups(st, &bytes, &len, 1, stream);  // (a group of one piece)
 }
 
 hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces, const uint64_t* lens,
@@ -256,116 +334,7 @@ hth_status hth_stream_update_gather(hth_stream* st, const uint8_t* const* pieces
   if (!pieces || !lens) return fail(HTH_E_INVALID, "hth_stream_update_gather: pieces or lens is null");
   for (uint32_t i = 0; i < count; ++i)
     if (lens[i] && !pieces[i]) return fail(HTH_E_INVALID, "hth_stream_update_gather: piece %u is null", i);
-  // (under stream capture every push stays on the captured stream)
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  hipError_t ce = hipStreamIsCapturing(stream, &cap);
-  if (ce != hipSuccess) return stream_fail(ce, "hth_stream_update_gather: capture status");
-  const bool on_side = cap == hipStreamCaptureStatusNone;
-  if (!on_side) {
-    hth_status js = join_side(st, stream);
-    if (js != HTH_OK) return js;
-  }
-  const uint64_t xb = st->xb;
-  for (uint32_t i = 0; i < count;) {
-    // a group: the carried bytes, then pieces while their table fits
-    hth::GatherArgs g{};
-    g.e0 = st->executions;
-    g.xb = (uint32_t)xb;
-    g.seg[0] = st->carry;
-    g.seg_len[0] = st->carry_len;
-    g.nseg = 1;
-    g.joins = st->joins;
-    g.carry = st->carry;
-    g.off = st->d_off;
-    g.len = st->d_len;
-    const int bsel = (int)(st->groups % 2);  // the group's roots and levels
-    uint64_t* const roots = bsel ? st->roots2 : st->roots;
-    g.lev = bsel ? st->d_lev2 : st->d_lev;
-    hth::GatherWalk w(xb, st->executions, st->carry_len);
-    uint32_t n = 0;  // table entries of the pieces taken (without the joins after the last)
-    uint64_t waves = 0, bytes = 0;
-    auto trailing = [](hth::GatherWalk f) {  // joins after the last piece's blocks
-      uint32_t c = 0;
-      f.finish([&](uint32_t, uint64_t) { ++c; });
-      return c;
-    };
-    for (; i < count && g.nseg <= hth::kGatherMax; ++i) {
-      if (lens[i] == 0) continue;
-      hth::GatherWalk t = w;
-      uint32_t tn = n;
-      uint64_t tw = waves;
-      t.piece(
-          pieces[i], lens[i],
-          [&](uint64_t, int L, const uint8_t*) {
-            ++tn;
-            tw += task_bound(xb << (3 * L), st->width, st->block);
-          },
-          [&](uint32_t, uint64_t) {
-            ++tn;
-            ++tw;
-          });
-      if (tn + trailing(t) > hth::kStreamTable) break;  // (one piece alone always fits: kMaxRoots + 1 entries)
-      g.w_at[g.nseg] = w.at;  // (the walk before the piece, for the table kernel)
-      g.w_next[g.nseg] = w.next;
-      g.w_nj[g.nseg] = w.nj;
-      g.w_first[g.nseg] = n;
-      g.seg[g.nseg] = pieces[i];
-      g.seg_len[g.nseg] = lens[i];
-      ++g.nseg;
-      w = t;
-      n = tn;
-      waves = tw;
-      bytes += lens[i];
-    }
-    if (g.nseg == 1) {
-      if (i < count) return fail(HTH_E_INVALID, "hth_stream_update_gather: piece %u does not fit a table", i);
-      break;  // (only empty pieces were left)
-    }
-    const uint32_t nt = trailing(w);
-    g.w_at[g.nseg] = w.at;
-    g.w_next[g.nseg] = w.next;
-    g.w_nj[g.nseg] = w.nj;
-    g.w_first[g.nseg] = n;
-    g.nj = w.nj + nt;
-    n += nt;
-    waves += nt;
-    const uint64_t nfull = w.at / xb;
-    g.nfull = nfull;
-    // table offsets from the lowest address the hashing kernel reads
-    uintptr_t lo = reinterpret_cast<uintptr_t>(st->joins);
-    for (uint32_t k = 1; k < g.nseg; ++k) lo = std::min(lo, reinterpret_cast<uintptr_t>(g.seg[k]));
-    g.base = reinterpret_cast<const uint8_t*>(lo);
-    // (the levels of buffer bsel were last read by the push two groups back)
-    hipError_t e = on_side ? hipStreamWaitEvent(stream, st->ev_push[bsel], 0) : hipSuccess;
-    if (e == hipSuccess) e = hth::launch_stream_gather(g, stream);
-    if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: table");
-    if (n) {
-      hth_status s = launch_blocks(st, g.base, n, waves, roots, stream);
-      if (s != HTH_OK) return s;
-      hipStream_t ps = stream;
-      if (on_side) {  // the push after this group's launch, beside the next group's work
-        e = hipEventRecord(st->ev_main[bsel], stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st->side, st->ev_main[bsel], 0);
-        if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: order the push");
-        ps = st->side;
-      }
-      const uint64_t* ent = st->seed->d_words + hth::entropy_offset_of(st->width, st->block);
-      e = hth::launch_stream_push(st->width, st->block, ent, st->carry, 0, nullptr, nullptr, 0, roots, g.lev, n,
-                                  st->stack, st->counts, ps);
-      if (e == hipSuccess && on_side) e = hipEventRecord(st->ev_push[bsel], st->side);
-      if (e != hipSuccess) return stream_fail(e, "hth_stream_update_gather: push launch");
-      if (on_side) {
-        st->last_push = st->ev_push[bsel];
-        st->push_pending = true;
-      }
-      ++st->groups;
-    }
-    const uint64_t all = st->carry_len + bytes;
-    st->executions += nfull;
-    st->carry_len = (uint32_t)(all - nfull * xb);
-    st->total_len += bytes;
-  }
-  return HTH_OK;
+  return append_groups(st, pieces, lens, count, stream);
 }
 
 hth_status hth_stream_final(hth_stream* st, uint8_t* out, hipStream_t stream) {
